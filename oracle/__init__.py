@@ -1,0 +1,174 @@
+"""CPU oracle for chains of elementary 3x3 geodesic dilations / erosions.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg.  The GPU library never imports or calls it.
+
+Thin ctypes front end over ``oracle.c`` (plain C, built by ``oracle/build.py``).
+Images are 2-D numpy arrays (rows = y, columns = x) of uint8, float32 or
+float64; they are converted exactly to float64 for the C code and the
+results are converted back to the input dtype, which is exact because
+min/max only select existing values (Section 2, Eq. 1-5).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+DILATE = 0
+ERODE = 1
+CODE_MASK = 9
+
+_P_D = ctypes.POINTER(ctypes.c_double)
+_P_U8 = ctypes.POINTER(ctypes.c_uint8)
+_I64 = ctypes.c_int64
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = None
+    lib.oracle_max_threads.argtypes = []
+    lib.oracle_max_threads.restype = ctypes.c_int
+    lib.oracle_step.argtypes = [ctypes.c_int, _P_D, _P_D, _P_D, _I64, _I64]
+    lib.oracle_step.restype = _I64
+    lib.oracle_chain.argtypes = [ctypes.c_int, _P_D, _P_D, _P_D, _I64, _I64, _I64]
+    lib.oracle_chain.restype = ctypes.c_int
+    lib.oracle_reconstruct.argtypes = [ctypes.c_int, _P_D, _P_D, _P_D, _I64, _I64, _I64,
+                                       ctypes.POINTER(_I64)]
+    lib.oracle_reconstruct.restype = ctypes.c_int
+    lib.oracle_chain_codes.argtypes = [ctypes.c_int, _P_D, _P_D, _P_D, _P_U8, _I64, _I64, _I64]
+    lib.oracle_chain_codes.restype = ctypes.c_int
+    lib.oracle_chain_grad.argtypes = [_P_U8, _P_D, _P_D, _P_D, _I64, _I64, _I64]
+    lib.oracle_chain_grad.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def set_threads(n: int) -> None:
+    _load().oracle_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
+
+
+def _op(op) -> int:
+    if op in (DILATE, "dilate", "dilation"):
+        return DILATE
+    if op in (ERODE, "erode", "erosion"):
+        return ERODE
+    raise ValueError(f"unknown op {op!r}")
+
+
+def _as_f64(a):
+    a = np.asarray(a)
+    if a.ndim != 2:
+        raise ValueError("images are 2-D (rows, columns)")
+    if a.dtype not in (np.uint8, np.float32, np.float64):
+        raise TypeError(f"unsupported dtype {a.dtype}")
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a, t=_P_D):
+    return a.ctypes.data_as(t) if a is not None else None
+
+
+def _back(a64, dtype):
+    out = a64.astype(dtype)
+    # min/max select existing values, so the round trip must be exact.
+    assert np.array_equal(out.astype(np.float64), a64)
+    return out
+
+
+def step(op, f, m=None):
+    """One elementary step delta_1^m / eps_1^m (plain delta_1 / eps_1 if m is None)."""
+    f64 = _as_f64(f)
+    m64 = _as_f64(m) if m is not None else None
+    if m64 is not None and m64.shape != f64.shape:
+        raise ValueError("marker and mask shapes differ")
+    out = np.empty_like(f64)
+    Y, X = f64.shape
+    _load().oracle_step(_op(op), _ptr(f64), _ptr(m64), _ptr(out), X, Y)
+    return _back(out, np.asarray(f).dtype)
+
+
+def chain(op, f, n, m=None):
+    """n-fold composition of the elementary step (Eq. 4); n = 0 is a copy."""
+    f64 = _as_f64(f)
+    m64 = _as_f64(m) if m is not None else None
+    if m64 is not None and m64.shape != f64.shape:
+        raise ValueError("marker and mask shapes differ")
+    if n < 0:
+        raise ValueError("n must be >= 0")
+    out = np.empty_like(f64)
+    Y, X = f64.shape
+    rc = _load().oracle_chain(_op(op), _ptr(f64), _ptr(m64), _ptr(out), X, Y, int(n))
+    if rc != 0:
+        raise MemoryError("oracle_chain failed")
+    return _back(out, np.asarray(f).dtype)
+
+
+def reconstruct(op, f, m, max_steps=-1):
+    """Reconstruction (Eq. 5).  Returns (result, steps_changed, converged)."""
+    f64 = _as_f64(f)
+    m64 = _as_f64(m)
+    if m64.shape != f64.shape:
+        raise ValueError("marker and mask shapes differ")
+    out = np.empty_like(f64)
+    Y, X = f64.shape
+    steps = _I64(0)
+    rc = _load().oracle_reconstruct(_op(op), _ptr(f64), _ptr(m64), _ptr(out), X, Y,
+                                    int(max_steps), ctypes.byref(steps))
+    if rc < 0:
+        raise MemoryError("oracle_reconstruct failed")
+    return _back(out, np.asarray(f).dtype), int(steps.value), rc == 0
+
+
+def chain_codes(op, f, n, m=None):
+    """Forward chain plus the per-step source code of every pixel.
+
+    Returns (result, codes) with codes of shape (n, Y, X), uint8: 0..8 is the
+    first extremal neighbour in raster (dy, dx) order, 9 means the mask won.
+    """
+    f64 = _as_f64(f)
+    m64 = _as_f64(m) if m is not None else None
+    Y, X = f64.shape
+    out = np.empty_like(f64)
+    codes = np.empty((int(n), Y, X), dtype=np.uint8)
+    rc = _load().oracle_chain_codes(_op(op), _ptr(f64), _ptr(m64), _ptr(out),
+                                    _ptr(codes, _P_U8), X, Y, int(n))
+    if rc != 0:
+        raise MemoryError("oracle_chain_codes failed")
+    return _back(out, np.asarray(f).dtype), codes
+
+
+def chain_grad(codes, g_out):
+    """Reverse pass by scattering.  Returns (grad_marker, grad_mask), float64."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    g64 = _as_f64(g_out)
+    n, Y, X = codes.shape
+    if g64.shape != (Y, X):
+        raise ValueError("gradient shape differs from the codes")
+    gf = np.empty_like(g64)
+    gm = np.empty_like(g64)
+    rc = _load().oracle_chain_grad(_ptr(codes, _P_U8), _ptr(g64), _ptr(gf), _ptr(gm),
+                                   X, Y, n)
+    if rc != 0:
+        raise MemoryError("oracle_chain_grad failed")
+    return gf, gm
+
+
+def chain_vjp(op, f, m, n, g_out):
+    """Gradient of sum(g_out * chain(op, f, n, m)) w.r.t. (f, m), float64."""
+    _, codes = chain_codes(op, f, n, m)
+    return chain_grad(codes, g_out)
