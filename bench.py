@@ -1,0 +1,189 @@
+"""Benchmark: Gpixel-steps/s of long 3x3 geodesic chains on one MI355X.
+
+One benchmark step = one 1500-step geodesic dilation chain over a 1024x1024
+uint8 image (mask = blurred noise, sigma 8; marker = mask - 40), inputs
+resident in HBM.  value = 1024*1024*1500 / (time per step) / 1e9.
+
+Also reported (same process, same GPU), each as Gpx-steps/s and as a ratio
+to the headline rate: the 1500-step geodesic erosion chain, reconstruction
+by dilation to stability, and the 13/91-step plain chains.  The roofline
+entry covers the chain kernel: 5 compare-selects per pixel-step (4 for the
+decomposed 3x3 window, 1 for the geodesic clamp) against the chip's dense
+compare-select rate.  The CPU baseline is the oracle on the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+import torch  # noqa: E402
+
+import workloads  # noqa: E402
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes = 64 VALU lane-ops per clock per CU at
+# 2.4 GHz; v_max3 / v_min3 perform two compare-selects per lane-op.
+PEAK_TCMP = 256 * 64 * 2.4e9 * 2 / 1e12   # 78.64 T compare-selects / s
+CMP_PER_PX_STEP_GEODESIC = 5
+CMP_PER_PX_STEP_PLAIN = 4
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--chain", type=int, default=1500)
+    ap.add_argument("--size", type=int, default=1024)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="headline chain only")
+    return ap.parse_args()
+
+
+def timed(fn, steps, warmup):
+    """ms per call of fn, timed with HIP events on the current stream."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(steps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / steps
+
+
+def kernel_profile(fn, steps):
+    """Average duration of the chain-kernel launches made by fn, from HIP
+    events the library records around each launch on the launch stream."""
+    import ctypes
+    from paper_1911_13074_amd import abi
+    torch.cuda.synchronize()
+    abi.check(abi.gc_profile_enable(1), "gc_profile_enable")
+    for _ in range(steps):
+        fn()
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    st = ctypes.c_int64()
+    abi.check(abi.gc_profile_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(st)),
+              "gc_profile_read")
+    abi.check(abi.gc_profile_enable(0), "gc_profile_enable")
+    return ms.value / max(n.value, 1), n.value, st.value
+
+
+def cpu_baseline(f, m, n_steps):
+    import oracle
+    threads = oracle.max_threads()
+    t0 = time.perf_counter()
+    oracle.chain(oracle.DILATE, f, n_steps, m)
+    dt = time.perf_counter() - t0
+    return {
+        "value": round(f.size * n_steps / dt / 1e9, 4),
+        "unit": "Gpixel-steps/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{f.shape[0]}x{f.shape[1]} u8, {n_steps}-step geodesic dilation chain "
+                  f"(the benchmark workload, {n_steps} of its steps), plain C oracle, "
+                  f"OpenMP over rows, {dt:.2f} s",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+    import paper_1911_13074_amd as gc
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    N, S = args.chain, args.size
+    f, m = workloads.headline_u8_dilation(size=S)
+    F = torch.from_numpy(f).to(dev)
+    M = torch.from_numpy(m).to(dev)
+    out = torch.empty_like(F)
+    px = F.numel()
+
+    def step():
+        gc.geodesic_dilate_chain(F, M, N, out=out)
+
+    ms = timed(step, args.steps, args.warmup)
+    value = px * N / (ms * 1e-3) / 1e9
+
+    k_ms, launches, k_steps = kernel_profile(step, max(2, min(args.steps, 5)))
+    steps_per_launch = k_steps / max(launches, 1)
+    achieved = CMP_PER_PX_STEP_GEODESIC * px * steps_per_launch / (k_ms * 1e-3) / 1e12
+    roofline = {
+        "bound": "alu",
+        "achieved": round(achieved, 3),
+        "peak": round(PEAK_TCMP, 2),
+        "unit": "Tcmp/s",
+        "frac": round(achieved / PEAK_TCMP, 4),
+        "traffic": None,
+        "kernel": "chain_block_kernel<u8, dilate, geodesic>",
+        "avg_launch_ms": round(k_ms, 5),
+        "steps_per_launch": round(steps_per_launch, 2),
+    }
+
+    extra = {}
+    if not args.no_extra:
+        fe, me = workloads.headline_u8_erosion(size=S)
+        Fe, Me = torch.from_numpy(fe).to(dev), torch.from_numpy(me).to(dev)
+        ms_e = timed(lambda: gc.geodesic_erode_chain(Fe, Me, N, out=out), max(3, args.steps // 4), 1)
+        extra["geodesic_erosion_1500"] = {"gpx_steps_per_s": round(px * N / ms_e / 1e6, 2),
+                                          "ms": round(ms_e, 4),
+                                          "vs_dilation": round(px * N / ms_e / 1e6 / value, 3)}
+        rec_steps = {}
+
+        def rec():
+            _, s_, _ = gc.reconstruct_by_dilation(F, M, out=out)
+            rec_steps["n"] = s_
+
+        ms_r = timed(rec, max(3, args.steps // 4), 1)
+        extra["reconstruction_by_dilation"] = {
+            "steps_changed": rec_steps["n"], "ms": round(ms_r, 4),
+            "gpx_steps_per_s": round(px * rec_steps["n"] / ms_r / 1e6, 2)}
+        for dt_name, dt in (("u8", np.uint8), ("f32", np.float32), ("f64", np.float64)):
+            x = torch.from_numpy(workloads.plain_input(dt, size=S)).to(dev)
+            y = torch.empty_like(x)
+            for n in (13, 91):
+                ms_p = timed(lambda: gc.dilate_chain(x, n, out=y), max(5, args.steps), 2)
+                extra[f"plain_dilation_{dt_name}_{n}"] = {
+                    "gpx_steps_per_s": round(px * n / ms_p / 1e6, 2), "ms": round(ms_p, 4)}
+
+    line = {
+        "metric": "Gpixel-steps/s, 1024² u8 1500-step geodesic chain",
+        "value": round(value, 2),
+        "unit": "Gpixel-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic (blurred uniform noise stands in for the paper's 1024x1024 test image)",
+        "config": {"workload": f"geodesic dilation chain, {S}x{S} u8, {N} steps, "
+                               "mask blur sigma 8, marker = mask - 40",
+                   "image": [S, S], "chain_steps": N, "global_batch": 1},
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(f, m, N)
+    line["extra"] = extra
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,17 @@
+"""MI355X (gfx950) library for long chains of elementary 3x3 geodesic
+dilations and erosions (Zlaus & Mongus, 2019).
+
+The computation lives in hand-written HIP kernels behind the C ABI of
+include/geochain.h (libgeochain.so); this package only marshals torch
+tensors to it.
+"""
+from .abi import GeochainError  # noqa: F401
+from .ops import (  # noqa: F401
+    dilate_chain,
+    erode_chain,
+    geodesic_dilate_chain,
+    geodesic_erode_chain,
+    reconstruct_by_dilation,
+    reconstruct_by_erosion,
+    set_tuning,
+)

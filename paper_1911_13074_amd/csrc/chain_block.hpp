@@ -1,0 +1,319 @@
+// chain_block.hpp -- temporal-blocked kernel for chains of elementary 3x3
+// geodesic (or plain) dilations / erosions on gfx950.
+//
+// One launch advances the image by k steps (Eq. 4 iterated k times).  Each
+// workgroup owns an output tile ("core") and loads the core plus a k-pixel
+// halo ("region") into REGISTERS.  It then runs k steps entirely on chip and
+// writes the core back.  Pixels near the region's outer edge see wrong
+// neighbours, but an error travels one pixel per step, so after k steps the
+// core is still exact.  This replaces the paper's CPU pipeline of in-place
+// streaming filters (Section 3.3-3.5): on the GPU the halo recomputation buys
+// k steps per trip to memory instead of one.
+//
+// Register layout (per workgroup of NW waves):
+//   region = (64*CW) columns x (NW*RPW) rows;
+//   wave w owns rows [w*RPW, (w+1)*RPW) of the region;
+//   lane l of a wave owns columns [l*CW, (l+1)*CW) of those rows.
+//
+// One step (Section 3.1: the 3x3 square decomposes into a 1x3 row pass and
+// a 3x1 column pass, 4 comparisons per pixel; Section 3.4 keeps the row-pass
+// results of neighbouring rows so each is computed once):
+//   1. row pass: h = extremum of (left, centre, right); the neighbour columns
+//      of the lane's edge pixels come from the adjacent lanes through DPP
+//      wave shifts (no memory traffic);
+//   2. the row-pass results of each wave's first and last rows go through
+//      LDS to the waves above and below (one barrier per step);
+//   3. column pass over the three row-pass results, then the geodesic clamp
+//      against the mask held in registers (Eq. 3).
+//
+// Image borders: pixels of the region outside the image hold the neutral
+// value (bottom for dilation, top for erosion) and a neutral mask, so the
+// clamp pins them to neutral every step; a neutral value never wins the
+// window extremum, which is exactly the clipped window of Section 2.
+//
+// Reconstruction (Eq. 5): for every step, each wave ORs "some core pixel
+// changed" into a per-launch bit mask (bit s = step s changed something),
+// which becomes a global word by one atomic OR per wave.  A launch whose
+// predecessor's word is not all-ones (the image had stopped changing)
+// exits at once; this is the GPU counterpart of the convergence flag of
+// Section 3.7.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace geochain {
+
+enum : int { OP_DILATE = 0, OP_ERODE = 1 };
+
+// Kernel mode: where the clamp mask comes from.
+enum : int {
+    MODE_GEODESIC = 0,   // mask read from memory (Eq. 3)
+    MODE_PLAIN = 1,      // no mask (Eq. 1-2); the clamp only fences the border
+};
+
+template <typename T> struct RegOf;
+template <> struct RegOf<uint8_t> { using type = uint32_t; };
+template <> struct RegOf<float> { using type = float; };
+template <> struct RegOf<double> { using type = double; };
+
+// bottom(OP): never wins the window extremum; top(OP): never wins the clamp.
+template <typename R, int OP> struct Bounds;
+template <> struct Bounds<uint32_t, OP_DILATE> {
+    static __device__ __forceinline__ uint32_t bottom() { return 0u; }
+    static __device__ __forceinline__ uint32_t top() { return 255u; }
+};
+template <> struct Bounds<uint32_t, OP_ERODE> {
+    static __device__ __forceinline__ uint32_t bottom() { return 255u; }
+    static __device__ __forceinline__ uint32_t top() { return 0u; }
+};
+template <> struct Bounds<float, OP_DILATE> {
+    static __device__ __forceinline__ float bottom() { return -__builtin_inff(); }
+    static __device__ __forceinline__ float top() { return __builtin_inff(); }
+};
+template <> struct Bounds<float, OP_ERODE> {
+    static __device__ __forceinline__ float bottom() { return __builtin_inff(); }
+    static __device__ __forceinline__ float top() { return -__builtin_inff(); }
+};
+template <> struct Bounds<double, OP_DILATE> {
+    static __device__ __forceinline__ double bottom() { return -__builtin_inf(); }
+    static __device__ __forceinline__ double top() { return __builtin_inf(); }
+};
+template <> struct Bounds<double, OP_ERODE> {
+    static __device__ __forceinline__ double bottom() { return __builtin_inf(); }
+    static __device__ __forceinline__ double top() { return -__builtin_inf(); }
+};
+
+// pick = the window extremum (max for dilation, min for erosion);
+// clamp = the geodesic constraint (min for dilation, max for erosion).
+template <int OP> struct Pick;
+template <> struct Pick<OP_DILATE> {
+    static __device__ __forceinline__ uint32_t pick(uint32_t a, uint32_t b) { return a > b ? a : b; }
+    static __device__ __forceinline__ float pick(float a, float b) { return __builtin_fmaxf(a, b); }
+    static __device__ __forceinline__ double pick(double a, double b) { return __builtin_fmax(a, b); }
+    static __device__ __forceinline__ uint32_t clamp(uint32_t a, uint32_t b) { return a < b ? a : b; }
+    static __device__ __forceinline__ float clamp(float a, float b) { return __builtin_fminf(a, b); }
+    static __device__ __forceinline__ double clamp(double a, double b) { return __builtin_fmin(a, b); }
+};
+template <> struct Pick<OP_ERODE> {
+    static __device__ __forceinline__ uint32_t pick(uint32_t a, uint32_t b) { return a < b ? a : b; }
+    static __device__ __forceinline__ float pick(float a, float b) { return __builtin_fminf(a, b); }
+    static __device__ __forceinline__ double pick(double a, double b) { return __builtin_fmin(a, b); }
+    static __device__ __forceinline__ uint32_t clamp(uint32_t a, uint32_t b) { return a > b ? a : b; }
+    static __device__ __forceinline__ float clamp(float a, float b) { return __builtin_fmaxf(a, b); }
+    static __device__ __forceinline__ double clamp(double a, double b) { return __builtin_fmax(a, b); }
+};
+
+// Cross-lane neighbours through DPP wave shifts.  from_left: lane i receives
+// lane i-1 (the pixel to its left); from_right: lane i receives lane i+1.
+// Lanes 0 / 63 receive 0: they sit on the region's outer edge, where wrong
+// values are tolerated (see the header comment).
+static constexpr int DPP_WAVE_SHR1 = 0x138;
+static constexpr int DPP_WAVE_SHL1 = 0x130;
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t lane_shift(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v) {
+    uint64_t u = __builtin_bit_cast(uint64_t, v);
+    uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, true);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ uint32_t to_reg(uint8_t v) { return v; }
+__device__ __forceinline__ float to_reg(float v) { return v; }
+__device__ __forceinline__ double to_reg(double v) { return v; }
+__device__ __forceinline__ void from_reg(uint8_t *p, uint32_t v) { *p = (uint8_t)v; }
+__device__ __forceinline__ void from_reg(float *p, float v) { *p = v; }
+__device__ __forceinline__ void from_reg(double *p, double v) { *p = v; }
+
+struct BlockArgs {
+    const void *src;       // state before the block (marker for the first)
+    const void *mask;      // mask image (geodesic mode), else unused
+    void *dst;             // state after the block (core pixels written)
+    int32_t width, height; // X, Y
+    int64_t pitch;         // elements
+    int32_t k;             // steps in this launch, 1 <= k
+    int32_t core_x, core_y;
+    int32_t tiles_x;
+    uint32_t *change_word;       // reconstruction: OR of per-step change bits
+    const uint32_t *prev_word;   // reconstruction: predecessor's word (or null)
+    uint32_t prev_full;          // value prev_word holds if every step changed
+};
+
+// One workgroup = one tile.  CLAMP=false is the plain-chain body for regions
+// that lie entirely inside the image (nothing to fence).
+template <typename T, int OP, int MODE, bool CLAMP, bool DETECT, int CW, int RPW, int NW>
+__device__ __forceinline__ void chain_block_body(const BlockArgs &a, int rx0, int ry0,
+                                                 typename RegOf<T>::type (*xch)[NW][2][64 * CW]) {
+    using R = typename RegOf<T>::type;
+    using B = Bounds<R, OP>;
+    using P = Pick<OP>;
+
+    const int lane = threadIdx.x & 63;
+    // wave index, known uniform: keeps the exchange branches scalar
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const T *src = static_cast<const T *>(a.src);
+    const T *msk = static_cast<const T *>(a.mask);
+    T *dst = static_cast<T *>(a.dst);
+    const int k = a.k;
+
+    R v[RPW][CW];
+    R m[CLAMP ? RPW : 1][CLAMP ? CW : 1];
+
+    // ---- load region (state and mask) ----
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        const int y = ry0 + w * RPW + r;
+        const bool yin = (unsigned)y < (unsigned)a.height;
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+            const int x = rx0 + lane * CW + c;
+            const bool in = yin && (unsigned)x < (unsigned)a.width;
+            const int64_t off = (int64_t)y * a.pitch + x;
+            v[r][c] = in ? to_reg(src[off]) : B::bottom();
+            if constexpr (CLAMP) {
+                if constexpr (MODE == MODE_GEODESIC)
+                    m[r][c] = in ? to_reg(msk[off]) : B::bottom();
+                else
+                    m[r][c] = in ? B::top() : B::bottom();
+            }
+        }
+    }
+
+    // Column ownership of the core, for change detection.
+    uint64_t col_in_core[CW];
+    if constexpr (DETECT) {
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+            const int cx = lane * CW + c;
+            const int x = rx0 + cx;
+            const bool ok = cx >= k && cx < k + a.core_x && x < a.width;
+            col_in_core[c] = __builtin_amdgcn_ballot_w64(ok);
+        }
+    }
+    uint32_t step_bits = 0;
+
+    for (int s = 0; s < k; ++s) {
+        // ---- 1. row pass ----
+        R h[RPW][CW];
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const R left = lane_shift<DPP_WAVE_SHR1>(v[r][CW - 1]);
+            const R right = lane_shift<DPP_WAVE_SHL1>(v[r][0]);
+            if constexpr (CW == 1) {
+                h[r][0] = P::pick(P::pick(left, v[r][0]), right);
+            } else if constexpr (CW == 2) {
+                // The pair's own extremum is shared by both outputs; each
+                // output then takes one cross-lane neighbour, which the
+                // compiler folds into a single DPP-sourced max/min.
+                const R t = P::pick(v[r][0], v[r][1]);
+                h[r][0] = P::pick(t, left);
+                h[r][1] = P::pick(t, right);
+            } else {
+#pragma unroll
+                for (int c = 0; c < CW; ++c) {
+                    const R l = c == 0 ? left : v[r][c - 1];
+                    const R rr = c == CW - 1 ? right : v[r][c + 1];
+                    h[r][c] = P::pick(P::pick(v[r][c], rr), l);
+                }
+            }
+        }
+        // ---- 2. exchange edge rows with the waves above and below ----
+        const int par = s & 1;
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+            xch[par][w][0][lane * CW + c] = h[0][c];
+            xch[par][w][1][lane * CW + c] = h[RPW - 1][c];
+        }
+        __syncthreads();
+        // The first (last) wave has no wave above (below); it reads its own
+        // opposite edge instead, a wrong but harmless value on the region's
+        // outer edge.  Branch-free, so the whole step is one basic block.
+        const int wa = w > 0 ? w - 1 : NW - 1;
+        const int wb = w < NW - 1 ? w + 1 : 0;
+        R above[CW], below[CW];
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+            above[c] = xch[par][wa][1][lane * CW + c];
+            below[c] = xch[par][wb][0][lane * CW + c];
+        }
+        // ---- 3. column pass + clamp ----
+        uint64_t changed = 0;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const int ry = w * RPW + r;
+            const bool row_in_core = DETECT && ry >= k && ry < k + a.core_y && ry0 + ry < a.height;
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                const R up = r == 0 ? above[c] : h[r - 1][c];
+                const R dn = r == RPW - 1 ? below[c] : h[r + 1][c];
+                R nv = P::pick(P::pick(up, h[r][c]), dn);
+                if constexpr (CLAMP) nv = P::clamp(nv, m[r][c]);
+                if constexpr (DETECT) {
+                    if (row_in_core)
+                        changed |= __builtin_amdgcn_ballot_w64(nv != v[r][c]) & col_in_core[c];
+                }
+                v[r][c] = nv;
+            }
+        }
+        if constexpr (DETECT) {
+            if (changed) step_bits |= 1u << s;
+        }
+    }
+
+    if constexpr (DETECT) {
+        if (step_bits != 0 && lane == 0) atomicOr(a.change_word, step_bits);
+    }
+
+    // ---- store the core ----
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        const int ry = w * RPW + r;
+        const int y = ry0 + ry;
+        const bool yok = ry >= k && ry < k + a.core_y && y < a.height;
+        if (!yok) continue;
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+            const int cx = lane * CW + c;
+            const int x = rx0 + cx;
+            if (cx >= k && cx < k + a.core_x && x < a.width)
+                from_reg(dst + (int64_t)y * a.pitch + x, v[r][c]);
+        }
+    }
+}
+
+template <typename T, int OP, int MODE, bool DETECT, int CW, int RPW, int NW>
+__global__ __launch_bounds__(64 * NW) void chain_block_kernel(BlockArgs a) {
+    if (DETECT && a.prev_word != nullptr) {
+        // The image stopped changing in an earlier launch: nothing to do.
+        if (*a.prev_word != a.prev_full) return;
+    }
+    const int tile = blockIdx.x;
+    const int tx = tile % a.tiles_x;
+    const int ty = tile / a.tiles_x;
+    const int rx0 = tx * a.core_x - a.k;
+    const int ry0 = ty * a.core_y - a.k;
+    constexpr int RX = 64 * CW;
+    constexpr int RY = NW * RPW;
+    using R = typename RegOf<T>::type;
+    __shared__ R xch[2][NW][2][RX];
+    if constexpr (MODE == MODE_PLAIN) {
+        const bool inside = rx0 >= 0 && ry0 >= 0 && rx0 + RX <= a.width && ry0 + RY <= a.height;
+        if (inside)
+            chain_block_body<T, OP, MODE, false, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
+        else
+            chain_block_body<T, OP, MODE, true, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
+    } else {
+        chain_block_body<T, OP, MODE, true, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
+    }
+}
+
+}  // namespace geochain

@@ -1,0 +1,141 @@
+"""Torch-facing calls of the geodesic chain library.
+
+Argument marshalling only: every function checks the tensors, passes their
+device pointers, shape, pitch and torch's current HIP stream to the C ABI
+(abi.py) and returns.  No step of the method runs here.
+
+Images are 2-D device tensors of dtype uint8, float32 or float64 whose rows
+are contiguous (stride(1) == 1); stride(0) is the row pitch.
+"""
+import ctypes
+
+import torch
+
+from . import abi
+
+_DTYPES = {torch.uint8: abi.GC_U8, torch.float32: abi.GC_F32, torch.float64: abi.GC_F64}
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    try:
+        return _DTYPES[t.dtype]
+    except KeyError:
+        raise TypeError(f"unsupported dtype {t.dtype}; use uint8, float32 or float64") from None
+
+
+def _check_image(t: torch.Tensor, name: str) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on a GPU device (got {t.device})")
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D (rows, columns), got shape {tuple(t.shape)}")
+    if t.size(1) > 1 and t.stride(1) != 1:
+        raise ValueError(f"{name} rows must be contiguous (stride(1) == 1)")
+
+
+def _shape(t: torch.Tensor) -> abi.gc_shape:
+    h, w = t.shape
+    pitch = t.stride(0) if h > 1 else max(w, 1)
+    return abi.gc_shape(w, h, max(pitch, w))
+
+
+def _same_layout(a: torch.Tensor, b: torch.Tensor, names: str) -> None:
+    if a.shape != b.shape or a.dtype != b.dtype or a.device != b.device:
+        raise ValueError(f"{names}: shape, dtype and device must match")
+    if a.size(0) > 1 and a.stride(0) != b.stride(0):
+        raise ValueError(f"{names}: row pitches differ")
+
+
+def _stream(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _out_like(t: torch.Tensor, out):
+    if out is None:
+        return torch.empty_like(t, memory_format=torch.contiguous_format) if t.is_contiguous() \
+            else torch.empty_strided(t.shape, t.stride(), dtype=t.dtype, device=t.device)
+    _check_image(out, "out")
+    _same_layout(t, out, "marker/out")
+    return out
+
+
+def _geodesic(fn_name, marker, mask, n_steps, out):
+    _check_image(marker, "marker")
+    _check_image(mask, "mask")
+    _same_layout(marker, mask, "marker/mask")
+    out = _out_like(marker, out)
+    with torch.cuda.device(marker.device):
+        st = getattr(abi, fn_name)(_dtype_code(marker), _ptr(marker), _ptr(mask), _ptr(out),
+                                   _shape(marker), int(n_steps), _stream(marker))
+    abi.check(st, fn_name)
+    return out
+
+
+def geodesic_dilate_chain(marker, mask, n_steps, out=None):
+    """n_steps elementary geodesic dilations min(delta_1(f), mask) (Eq. 3-4)."""
+    return _geodesic("gc_geodesic_dilate_chain", marker, mask, n_steps, out)
+
+
+def geodesic_erode_chain(marker, mask, n_steps, out=None):
+    """n_steps elementary geodesic erosions max(eps_1(f), mask) (Eq. 3-4)."""
+    return _geodesic("gc_geodesic_erode_chain", marker, mask, n_steps, out)
+
+
+def _plain(fn_name, x, n_steps, out):
+    _check_image(x, "input")
+    out = _out_like(x, out)
+    with torch.cuda.device(x.device):
+        st = getattr(abi, fn_name)(_dtype_code(x), _ptr(x), _ptr(out), _shape(x), int(n_steps),
+                                   _stream(x))
+    abi.check(st, fn_name)
+    return out
+
+
+def dilate_chain(x, n_steps, out=None):
+    """n_steps plain 3x3 dilations = one (2n+1)^2 clipped window max (Eq. 2)."""
+    return _plain("gc_dilate_chain", x, n_steps, out)
+
+
+def erode_chain(x, n_steps, out=None):
+    """n_steps plain 3x3 erosions = one (2n+1)^2 clipped window min (Eq. 1)."""
+    return _plain("gc_erode_chain", x, n_steps, out)
+
+
+def _reconstruct(fn_name, marker, mask, max_steps, out, allow_not_converged):
+    _check_image(marker, "marker")
+    _check_image(mask, "mask")
+    _same_layout(marker, mask, "marker/mask")
+    out = _out_like(marker, out)
+    steps = ctypes.c_int64(0)
+    with torch.cuda.device(marker.device):
+        st = getattr(abi, fn_name)(_dtype_code(marker), _ptr(marker), _ptr(mask), _ptr(out),
+                                   _shape(marker), int(max_steps), ctypes.byref(steps),
+                                   _stream(marker))
+    if st == abi.GC_ERR_NOT_CONVERGED and allow_not_converged:
+        return out, int(steps.value), False
+    abi.check(st, fn_name)
+    return out, int(steps.value), True
+
+
+def reconstruct_by_dilation(marker, mask, max_steps=-1, out=None, allow_not_converged=False):
+    """Reconstruction by dilation (Eq. 5).  Returns (image, steps_changed,
+    converged); synchronises the current stream."""
+    return _reconstruct("gc_reconstruct_by_dilation", marker, mask, max_steps, out,
+                        allow_not_converged)
+
+
+def reconstruct_by_erosion(marker, mask, max_steps=-1, out=None, allow_not_converged=False):
+    """Reconstruction by erosion (Eq. 5).  Returns (image, steps_changed,
+    converged); synchronises the current stream."""
+    return _reconstruct("gc_reconstruct_by_erosion", marker, mask, max_steps, out,
+                        allow_not_converged)
+
+
+def set_tuning(block_steps: int = 0, tile: int = -1) -> None:
+    """Override steps per launch and tile family (0 / -1: built-in choice)."""
+    abi.check(abi.gc_set_tuning(int(block_steps), int(tile)), "gc_set_tuning")

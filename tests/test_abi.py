@@ -1,0 +1,92 @@
+"""The C-ABI library loads and exports what include/geochain.h declares, and
+its host-side argument checks answer before any GPU work (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1911_13074_amd import abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"\b(gc_\w+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = abi.load()
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_every_declared_symbol():
+    assert set(declared_functions()) == set(abi.SIGNATURES)
+
+
+def test_status_strings():
+    assert abi.status_string(0) == "GC_OK"
+    assert abi.status_string(-3) == "GC_ERR_ALIAS"
+    assert abi.status_string(-6) == "GC_ERR_NOT_CONVERGED"
+    assert abi.status_string(-99) == "GC_ERR_UNKNOWN"
+    assert abi.gc_version() >= 100
+
+
+def shape(w, h, p):
+    return abi.gc_shape(w, h, p)
+
+
+FAKE = 1 << 40  # never dereferenced: every call below fails validation first
+
+
+@pytest.mark.parametrize("call", [
+    # pitch < width
+    lambda: abi.gc_geodesic_dilate_chain(abi.GC_U8, FAKE, FAKE + (1 << 20), FAKE + (2 << 20),
+                                         shape(10, 10, 9), 3, None),
+    # negative size
+    lambda: abi.gc_dilate_chain(abi.GC_F32, FAKE, FAKE + (1 << 20), shape(-1, 10, 10), 3, None),
+    # unknown dtype
+    lambda: abi.gc_erode_chain(7, FAKE, FAKE + (1 << 20), shape(4, 4, 4), 1, None),
+    # negative steps
+    lambda: abi.gc_geodesic_erode_chain(abi.GC_F64, FAKE, FAKE + (1 << 20), FAKE + (2 << 20),
+                                        shape(4, 4, 4), -2, None),
+    # null pointers on a non-empty image
+    lambda: abi.gc_geodesic_dilate_chain(abi.GC_U8, None, FAKE, FAKE + (1 << 20),
+                                         shape(4, 4, 4), 1, None),
+    lambda: abi.gc_geodesic_dilate_chain(abi.GC_U8, FAKE, None, FAKE + (1 << 20),
+                                         shape(4, 4, 4), 1, None),
+])
+def test_invalid_arguments(call):
+    assert call() == abi.GC_ERR_INVALID_ARG
+    assert abi.last_error() != ""
+
+
+def test_aliasing_is_rejected():
+    s = shape(100, 100, 128)
+    # out == mask
+    assert abi.gc_geodesic_dilate_chain(abi.GC_U8, FAKE, FAKE + (1 << 20), FAKE + (1 << 20),
+                                        s, 5, None) == abi.GC_ERR_ALIAS
+    # out overlaps the mask's last row
+    assert abi.gc_geodesic_erode_chain(abi.GC_F32, FAKE, FAKE + (1 << 20),
+                                       FAKE + (1 << 20) + 4 * 99 * 128, s, 5,
+                                       None) == abi.GC_ERR_ALIAS
+    # out partially overlaps the input of a plain chain
+    assert abi.gc_dilate_chain(abi.GC_F64, FAKE, FAKE + 8, s, 5, None) == abi.GC_ERR_ALIAS
+    steps = ctypes.c_int64(7)
+    assert abi.gc_reconstruct_by_dilation(abi.GC_U8, FAKE, FAKE + (1 << 20), FAKE + (1 << 20), s,
+                                          -1, ctypes.byref(steps), None) == abi.GC_ERR_ALIAS
+
+
+def test_tuning_hook_validates():
+    assert abi.gc_set_tuning(64, -1) == abi.GC_ERR_INVALID_ARG
+    assert abi.gc_set_tuning(4, 9) == abi.GC_ERR_INVALID_ARG
+    assert abi.gc_set_tuning(0, -1) == abi.GC_OK

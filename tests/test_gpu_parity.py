@@ -1,0 +1,262 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle,
+element by element and bit-exact (min/max only select existing values, so
+every dtype must match exactly), on the same seeded inputs.
+
+Covers: the small 256x256 workload, ragged shapes that span several tiles
+with partial tiles at the right and bottom, 1-pixel-wide images, padded row
+pitches, in-place calls, zero steps, empty images, sweeps of the launch
+shape (steps per launch and tile family), reconstruction step counts, the
+step cap, and the full-size 1024x1024 workloads in the launch configuration
+the benchmark times.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+import paper_1911_13074_amd as gc
+from paper_1911_13074_amd import abi
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [np.uint8, np.float32, np.float64]
+OPS = [oracle.DILATE, oracle.ERODE]
+
+
+@pytest.fixture(autouse=True)
+def _reset_tuning():
+    yield
+    gc.set_tuning(0, -1)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rand_pair(shape, dtype, seed, levels=None):
+    """Marker / mask with plateaus and ties (few levels) or full range."""
+    rng = np.random.default_rng(seed)
+    if np.dtype(dtype) == np.uint8:
+        hi = 256 if levels is None else levels
+        f = rng.integers(0, hi, size=shape).astype(np.uint8)
+        m = rng.integers(0, hi, size=shape).astype(np.uint8)
+        if levels is not None:
+            f = (f * (255 // (levels - 1))).astype(np.uint8)
+            m = (m * (255 // (levels - 1))).astype(np.uint8)
+        return f, m
+    if levels is not None:
+        f = (rng.integers(0, levels, size=shape) - levels / 2).astype(dtype)
+        m = (rng.integers(0, levels, size=shape) - levels / 2).astype(dtype)
+        return f, m
+    return rng.standard_normal(shape).astype(dtype), rng.standard_normal(shape).astype(dtype)
+
+
+def gpu_chain(op, f, m, n, **kw):
+    fn = gc.geodesic_dilate_chain if op == oracle.DILATE else gc.geodesic_erode_chain
+    return host(fn(dev(f), dev(m), n, **kw))
+
+
+def gpu_plain(op, f, n):
+    fn = gc.dilate_chain if op == oracle.DILATE else gc.erode_chain
+    return host(fn(dev(f), n))
+
+
+def assert_same(got, expect, what=""):
+    assert got.dtype == expect.dtype, what
+    if not np.array_equal(got, expect):
+        bad = np.argwhere(got != expect)
+        y, x = bad[0]
+        raise AssertionError(f"{what}: {len(bad)} pixels differ, first at (y={y}, x={x}): "
+                             f"got {got[y, x]!r} expected {expect[y, x]!r}")
+
+
+# --------------------------------------------------------------------------
+# the 256x256 u8 workload: 50 geodesic dilations and reconstruction
+# --------------------------------------------------------------------------
+def test_small_u8_workload():
+    f, m = workloads.small_u8()
+    assert_same(gpu_chain(oracle.DILATE, f, m, 50), oracle.chain(oracle.DILATE, f, 50, m), "chain")
+    out, steps, conv = gc.reconstruct_by_dilation(dev(f), dev(m))
+    ref, ref_steps, ref_conv = oracle.reconstruct(oracle.DILATE, f, m)
+    assert conv and ref_conv
+    assert steps == ref_steps
+    assert_same(host(out), ref, "reconstruction")
+
+
+# --------------------------------------------------------------------------
+# ragged shapes, all dtypes, both operations
+# --------------------------------------------------------------------------
+SHAPES = [(1, 1), (1, 300), (300, 1), (67, 129), (200, 517), (513, 385)]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("shape", SHAPES)
+def test_geodesic_chain_ragged(dtype, op, shape):
+    for i, n in enumerate((1, 7, 45)):
+        f, m = rand_pair(shape, dtype, seed=hash((shape, n)) % 10007, levels=(6 if i % 2 else None))
+        assert_same(gpu_chain(op, f, m, n), oracle.chain(op, f, n, m), f"n={n}")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("shape", SHAPES)
+def test_plain_chain_ragged(dtype, op, shape):
+    for n in (1, 13, 40):
+        f, _ = rand_pair(shape, dtype, seed=n + 17)
+        assert_same(gpu_plain(op, f, n), oracle.chain(op, f, n), f"n={n}")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_padded_pitch(dtype):
+    h, w, pitch = 150, 203, 256
+    f, m = rand_pair((h, w), dtype, seed=3)
+    F = torch.zeros((h, pitch), dtype=dev(f).dtype, device="cuda")
+    M = torch.zeros_like(F)
+    F[:, :w] = dev(f)
+    M[:, :w] = dev(m)
+    fv, mv = F[:, :w], M[:, :w]
+    assert fv.stride(0) == pitch
+    out = gc.geodesic_dilate_chain(fv, mv, 37)
+    assert out.stride(0) == pitch
+    assert_same(host(out), oracle.chain(oracle.DILATE, f, 37, m), "geodesic")
+    out = gc.erode_chain(fv, 21)
+    assert_same(host(out), oracle.chain(oracle.ERODE, f, 21), "plain")
+    # padding columns of the inputs were not touched
+    assert torch.all(F[:, w:] == 0) and torch.all(M[:, w:] == 0)
+
+
+@pytest.mark.parametrize("n", [1, 2, 31, 32, 33, 64, 65, 100])
+def test_in_place(n):
+    f, m = rand_pair((140, 333), np.uint8, seed=n)
+    F, M = dev(f), dev(m)
+    out = gc.geodesic_dilate_chain(F, M, n, out=F)
+    assert out.data_ptr() == F.data_ptr()
+    assert_same(host(F), oracle.chain(oracle.DILATE, f, n, m), "geodesic in place")
+    G = dev(f)
+    gc.erode_chain(G, n, out=G)
+    assert_same(host(G), oracle.chain(oracle.ERODE, f, n), "plain in place")
+
+
+def test_zero_steps_and_empty():
+    f, m = rand_pair((50, 70), np.float32, seed=1)
+    assert_same(gpu_chain(oracle.DILATE, f, m, 0), f, "n=0 copies the marker")
+    e = torch.empty((0, 9), dtype=torch.uint8, device="cuda")
+    assert gc.geodesic_dilate_chain(e, e.clone(), 5).shape == (0, 9)
+    e2 = torch.empty((7, 0), dtype=torch.float64, device="cuda")
+    assert gc.dilate_chain(e2, 3).shape == (7, 0)
+    out, steps, conv = gc.reconstruct_by_erosion(e2, e2.clone())
+    assert steps == 0 and conv
+
+
+@pytest.mark.parametrize("tile", [0, 1])
+@pytest.mark.parametrize("k", [1, 3, 16, 24, 32, 47])
+def test_launch_shape_sweep(tile, k):
+    if tile == 1 and k > 24:
+        pytest.skip("the 64x64 tile family keeps a core of >= 16 only up to 24 steps")
+    gc.set_tuning(k, tile)
+    for dtype in DTYPES:
+        f, m = rand_pair((311, 517), dtype, seed=k * 7 + tile, levels=9)
+        assert_same(gpu_chain(oracle.DILATE, f, m, 100), oracle.chain(oracle.DILATE, f, 100, m),
+                    f"{np.dtype(dtype)} k={k} tile={tile}")
+
+
+# --------------------------------------------------------------------------
+# reconstruction (Eq. 5)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("shape", [(1, 1), (1, 257), (96, 1), (127, 200), (300, 417)])
+def test_reconstruction_parity(dtype, op, shape):
+    f, m = rand_pair(shape, dtype, seed=len(shape) + shape[0], levels=12)
+    fn = gc.reconstruct_by_dilation if op == oracle.DILATE else gc.reconstruct_by_erosion
+    out, steps, conv = fn(dev(f), dev(m))
+    ref, ref_steps, ref_conv = oracle.reconstruct(op, f, m)
+    assert conv and ref_conv
+    assert steps == ref_steps
+    assert_same(host(out), ref, "reconstruction")
+
+
+def serpentine(rows, width):
+    Y = 2 * rows - 1
+    m = np.zeros((Y, width), dtype=np.uint8)
+    for r in range(rows):
+        m[2 * r, :] = 1
+        if r < rows - 1:
+            m[2 * r + 1, width - 1 if r % 2 == 0 else 0] = 1
+    return m
+
+
+def test_long_reconstruction_and_cap():
+    m = serpentine(40, 300)        # a corridor of ~12000 steps
+    f = np.zeros_like(m)
+    f[0, 0] = 1
+    ref, ref_steps, conv = oracle.reconstruct(oracle.DILATE, f, m)
+    assert conv and ref_steps > 10000
+    out, steps, conv = gc.reconstruct_by_dilation(dev(f), dev(m))
+    assert conv and steps == ref_steps
+    assert_same(host(out), ref, "serpentine")
+    # cap below the length: NOT_CONVERGED with the chain of max_steps
+    cap = ref_steps - 37
+    out, steps, conv = gc.reconstruct_by_dilation(dev(f), dev(m), max_steps=cap,
+                                                  allow_not_converged=True)
+    assert not conv and steps == cap
+    assert_same(host(out), oracle.chain(oracle.DILATE, f, cap, m), "capped")
+    with pytest.raises(abi.GeochainError) as ei:
+        gc.reconstruct_by_dilation(dev(f), dev(m), max_steps=cap)
+    assert ei.value.status == abi.GC_ERR_NOT_CONVERGED
+    # cap exactly at the length: converged
+    out, steps, conv = gc.reconstruct_by_dilation(dev(f), dev(m), max_steps=ref_steps)
+    assert conv and steps == ref_steps
+    assert_same(host(out), ref, "cap == length")
+
+
+def test_reconstruction_in_place_and_marker_above_mask():
+    f, m = rand_pair((200, 260), np.float32, seed=99, levels=10)   # f not <= m
+    F = dev(f)
+    out, steps, conv = gc.reconstruct_by_dilation(F, dev(m), out=F)
+    ref, ref_steps, _ = oracle.reconstruct(oracle.DILATE, f, m)
+    assert conv and steps == ref_steps
+    assert_same(host(F), ref, "in place")
+
+
+# --------------------------------------------------------------------------
+# full-size workloads (the configuration the benchmark times)
+# --------------------------------------------------------------------------
+def test_headline_1024_u8_1500_steps():
+    f, m = workloads.headline_u8_dilation()
+    assert_same(gpu_chain(oracle.DILATE, f, m, 1500), oracle.chain(oracle.DILATE, f, 1500, m),
+                "geodesic dilation x1500")
+    f, m = workloads.headline_u8_erosion()
+    assert_same(gpu_chain(oracle.ERODE, f, m, 1500), oracle.chain(oracle.ERODE, f, 1500, m),
+                "geodesic erosion x1500")
+
+
+def test_headline_reconstruction():
+    f, m = workloads.headline_u8_dilation()
+    out, steps, conv = gc.reconstruct_by_dilation(dev(f), dev(m))
+    ref, ref_steps, ref_conv = oracle.reconstruct(oracle.DILATE, f, m)
+    assert conv and ref_conv and steps == ref_steps
+    assert_same(host(out), ref, "reconstruction")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [13, 91])
+def test_plain_1024_window_equivalents(dtype, n):
+    x = workloads.plain_input(dtype)
+    for op in OPS:
+        assert_same(gpu_plain(op, x, n), oracle.chain(op, x, n), f"op={op}")
+
+
+def test_repeat_determinism():
+    f, m = workloads.headline_u8_dilation()
+    F, M = dev(f), dev(m)
+    a = host(gc.geodesic_dilate_chain(F, M, 777))
+    for _ in range(3):
+        assert np.array_equal(host(gc.geodesic_dilate_chain(F, M, 777)), a)
