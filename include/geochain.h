@@ -123,6 +123,69 @@ int gc_reconstruct_by_erosion(gc_dtype dtype, const void *marker, const void *ma
                               int64_t *steps_out, void *hip_stream);
 
 /* ---------------------------------------------------------------------
+ * Batches: many independent chains (Eq. 4), each with its own image size
+ * and number of steps, run by ONE persistent kernel launch recorded in a
+ * HIP graph.  There is no batching in the paper; its closest analogue is
+ * keeping many filters of a chain in flight at once (Section 3.5).
+ *
+ * gc_item: marker / mask / out are device pointers (same rules as the
+ * single-image calls: out may equal marker, must not overlap mask).  All
+ * items of one plan must be geodesic (mask != NULL) or all plain (mask ==
+ * NULL).  n_steps >= 0.
+ *
+ * gc_plan_create validates the items, chooses the tile family and steps per
+ * block (from the autotuner's table when it has an entry for the items'
+ * size class, see gc_autotune), builds the work list, allocates the plan's
+ * workspace (two work images per item plus counters) and records the launch
+ * into a HIP graph.  It copies the gc_item array; the images themselves
+ * must stay allocated while the plan is used.  It synchronises the device
+ * stream it uses for recording.
+ *
+ * gc_plan_launch replays the graph on hip_stream (asynchronous).  Launches
+ * of one plan must not overlap each other (they share the workspace).
+ *
+ * gc_plan_status waits for the plan's last launch and returns GC_OK, or
+ * GC_ERR_HIP if a dependency wait inside the kernel hit its safety bound
+ * (results then invalid).
+ *
+ * gc_plan_info reports totals of the plan (any pointer may be NULL):
+ * pixel-steps per launch, work items, workgroups launched, tile family and
+ * the largest steps-per-block used.
+ * ------------------------------------------------------------------- */
+typedef struct {
+    const void *marker;
+    const void *mask;
+    void *out;
+    gc_shape shape;
+    int64_t n_steps;
+} gc_item;
+
+typedef struct gc_plan gc_plan;
+
+int gc_plan_create(gc_dtype dtype, gc_op op, const gc_item *items, int32_t n_items,
+                   gc_plan **plan_out);
+int gc_plan_launch(gc_plan *plan, void *hip_stream);
+int gc_plan_status(gc_plan *plan);
+int gc_plan_info(const gc_plan *plan, int64_t *px_steps, int64_t *work_items,
+                 int32_t *workgroups, int32_t *tile, int32_t *block_steps);
+int gc_plan_destroy(gc_plan *plan);
+
+/* ---------------------------------------------------------------------
+ * Autotuner.  Times every candidate (tile family x steps per block) of the
+ * persistent kernel on scratch images of the given size class and records
+ * the fastest in a process-wide table that gc_plan_create and the
+ * single-image chains consult.  Size class = (ceil(log2 width),
+ * ceil(log2 height)).  geodesic != 0 tunes the geodesic kernel, else the
+ * plain one.  Synchronises the device; allocates scratch memory.
+ * best_tile / best_k (may be NULL) receive the choice.
+ * ------------------------------------------------------------------- */
+int gc_autotune(gc_dtype dtype, gc_op op, int32_t geodesic, int64_t width, int64_t height,
+                int32_t *best_tile, int32_t *best_k);
+
+/* Drop every autotuner entry. */
+int gc_autotune_clear(void);
+
+/* ---------------------------------------------------------------------
  * Tuning hook: override the temporal-block depth (steps fused per launch)
  * and the tile family used by the chain kernels.  block_steps = 0 and
  * tile = -1 restore the built-in choice.  Process-wide; intended for the

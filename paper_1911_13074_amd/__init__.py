@@ -7,6 +7,9 @@ tensors to it.
 """
 from .abi import GeochainError  # noqa: F401
 from .ops import (  # noqa: F401
+    BatchPlan,
+    autotune,
+    autotune_clear,
     dilate_chain,
     erode_chain,
     geodesic_dilate_chain,

@@ -26,6 +26,11 @@ class gc_shape(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int64), ("height", ctypes.c_int64), ("pitch", ctypes.c_int64)]
 
 
+class gc_item(ctypes.Structure):
+    _fields_ = [("marker", ctypes.c_void_p), ("mask", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("shape", gc_shape), ("n_steps", ctypes.c_int64)]
+
+
 class GeochainError(RuntimeError):
     def __init__(self, status, func, detail):
         self.status = status
@@ -50,6 +55,16 @@ SIGNATURES = {
     "gc_reconstruct_by_dilation": (ctypes.c_int, [_DT, _VP, _VP, _VP, gc_shape, _I64, _P_I64, _VP]),
     "gc_reconstruct_by_erosion": (ctypes.c_int, [_DT, _VP, _VP, _VP, gc_shape, _I64, _P_I64, _VP]),
     "gc_set_tuning": (ctypes.c_int, [_I32, _I32]),
+    "gc_plan_create": (ctypes.c_int, [_DT, _DT, ctypes.POINTER(gc_item), _I32,
+                                      ctypes.POINTER(ctypes.c_void_p)]),
+    "gc_plan_launch": (ctypes.c_int, [_VP, _VP]),
+    "gc_plan_status": (ctypes.c_int, [_VP]),
+    "gc_plan_info": (ctypes.c_int, [_VP, _P_I64, _P_I64, ctypes.POINTER(_I32),
+                                    ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "gc_plan_destroy": (ctypes.c_int, [_VP]),
+    "gc_autotune": (ctypes.c_int, [_DT, _DT, _I32, _I64, _I64, ctypes.POINTER(_I32),
+                                   ctypes.POINTER(_I32)]),
+    "gc_autotune_clear": (ctypes.c_int, []),
     "gc_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "gc_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), _P_I64, _P_I64]),
 }

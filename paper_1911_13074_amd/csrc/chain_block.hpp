@@ -140,7 +140,8 @@ struct BlockArgs {
     void *dst;             // state after the block (core pixels written)
     int32_t width, height; // X, Y
     int64_t pitch;         // elements
-    int32_t k;             // steps in this launch, 1 <= k
+    int32_t k;             // steps in this launch, 1 <= k <= halo
+    int32_t halo;          // offset of the core inside the region
     int32_t core_x, core_y;
     int32_t tiles_x;
     uint32_t *change_word;       // reconstruction: OR of per-step change bits
@@ -150,9 +151,12 @@ struct BlockArgs {
 
 // One workgroup = one tile.  CLAMP=false is the plain-chain body for regions
 // that lie entirely inside the image (nothing to fence).
+// Runs a.k steps on the region whose top-left corner is (rx0, ry0) and
+// writes its core (offset a.halo, size core_x x core_y).  With DETECT, returns
+// this wave's change bits (bit s: some core pixel changed at step s).
 template <typename T, int OP, int MODE, bool CLAMP, bool DETECT, int CW, int RPW, int NW>
-__device__ __forceinline__ void chain_block_body(const BlockArgs &a, int rx0, int ry0,
-                                                 typename RegOf<T>::type (*xch)[NW][2][64 * CW]) {
+__device__ __forceinline__ uint32_t chain_block_body(const BlockArgs &a, int rx0, int ry0,
+                                                     typename RegOf<T>::type (*xch)[NW][2][64 * CW]) {
     using R = typename RegOf<T>::type;
     using B = Bounds<R, OP>;
     using P = Pick<OP>;
@@ -164,6 +168,7 @@ __device__ __forceinline__ void chain_block_body(const BlockArgs &a, int rx0, in
     const T *msk = static_cast<const T *>(a.mask);
     T *dst = static_cast<T *>(a.dst);
     const int k = a.k;
+    const int halo = a.halo;
 
     R v[RPW][CW];
     R m[CLAMP ? RPW : 1][CLAMP ? CW : 1];
@@ -195,7 +200,7 @@ __device__ __forceinline__ void chain_block_body(const BlockArgs &a, int rx0, in
         for (int c = 0; c < CW; ++c) {
             const int cx = lane * CW + c;
             const int x = rx0 + cx;
-            const bool ok = cx >= k && cx < k + a.core_x && x < a.width;
+            const bool ok = cx >= halo && cx < halo + a.core_x && x < a.width;
             col_in_core[c] = __builtin_amdgcn_ballot_w64(ok);
         }
     }
@@ -250,7 +255,7 @@ __device__ __forceinline__ void chain_block_body(const BlockArgs &a, int rx0, in
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
             const int ry = w * RPW + r;
-            const bool row_in_core = DETECT && ry >= k && ry < k + a.core_y && ry0 + ry < a.height;
+            const bool row_in_core = DETECT && ry >= halo && ry < halo + a.core_y && ry0 + ry < a.height;
 #pragma unroll
             for (int c = 0; c < CW; ++c) {
                 const R up = r == 0 ? above[c] : h[r - 1][c];
@@ -269,24 +274,36 @@ __device__ __forceinline__ void chain_block_body(const BlockArgs &a, int rx0, in
         }
     }
 
-    if constexpr (DETECT) {
-        if (step_bits != 0 && lane == 0) atomicOr(a.change_word, step_bits);
-    }
-
     // ---- store the core ----
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
         const int ry = w * RPW + r;
         const int y = ry0 + ry;
-        const bool yok = ry >= k && ry < k + a.core_y && y < a.height;
+        const bool yok = ry >= halo && ry < halo + a.core_y && y < a.height;
         if (!yok) continue;
 #pragma unroll
         for (int c = 0; c < CW; ++c) {
             const int cx = lane * CW + c;
             const int x = rx0 + cx;
-            if (cx >= k && cx < k + a.core_x && x < a.width)
+            if (cx >= halo && cx < halo + a.core_x && x < a.width)
                 from_reg(dst + (int64_t)y * a.pitch + x, v[r][c]);
         }
+    }
+    return step_bits;
+}
+
+// Plain chains skip the border fence for regions entirely inside the image.
+template <typename T, int OP, int MODE, bool DETECT, int CW, int RPW, int NW>
+__device__ __forceinline__ uint32_t chain_block_dispatch(const BlockArgs &a, int rx0, int ry0,
+                                                         typename RegOf<T>::type (*xch)[NW][2][64 * CW]) {
+    constexpr int RX = 64 * CW;
+    constexpr int RY = NW * RPW;
+    if constexpr (MODE == MODE_PLAIN) {
+        const bool inside = rx0 >= 0 && ry0 >= 0 && rx0 + RX <= a.width && ry0 + RY <= a.height;
+        if (inside) return chain_block_body<T, OP, MODE, false, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
+        return chain_block_body<T, OP, MODE, true, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
+    } else {
+        return chain_block_body<T, OP, MODE, true, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
     }
 }
 
@@ -299,20 +316,13 @@ __global__ __launch_bounds__(64 * NW) void chain_block_kernel(BlockArgs a) {
     const int tile = blockIdx.x;
     const int tx = tile % a.tiles_x;
     const int ty = tile / a.tiles_x;
-    const int rx0 = tx * a.core_x - a.k;
-    const int ry0 = ty * a.core_y - a.k;
-    constexpr int RX = 64 * CW;
-    constexpr int RY = NW * RPW;
+    const int rx0 = tx * a.core_x - a.halo;
+    const int ry0 = ty * a.core_y - a.halo;
     using R = typename RegOf<T>::type;
-    __shared__ R xch[2][NW][2][RX];
-    if constexpr (MODE == MODE_PLAIN) {
-        const bool inside = rx0 >= 0 && ry0 >= 0 && rx0 + RX <= a.width && ry0 + RY <= a.height;
-        if (inside)
-            chain_block_body<T, OP, MODE, false, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
-        else
-            chain_block_body<T, OP, MODE, true, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
-    } else {
-        chain_block_body<T, OP, MODE, true, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
+    __shared__ R xch[2][NW][2][64 * CW];
+    const uint32_t bits = chain_block_dispatch<T, OP, MODE, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
+    if constexpr (DETECT) {
+        if (bits != 0 && (threadIdx.x & 63) == 0) atomicOr(a.change_word, bits);
     }
 }
 

@@ -5,17 +5,20 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
 #include "geochain.h"
 #include "chain_block.hpp"
+#include "persistent.hpp"
 
 namespace geochain {
 
@@ -362,6 +365,7 @@ static int run_chain(gc_dtype dtype, int op, int mode, const void *src, const vo
         a.height = (int32_t)s.height;
         a.pitch = s.pitch;
         a.k = ks[i];
+        a.halo = ks[i];
         a.core_x = g.core_x;
         a.core_y = g.core_y;
         a.tiles_x = g.tiles_x;
@@ -411,6 +415,7 @@ static int run_reconstruct(gc_dtype dtype, int op, const void *marker, const voi
         a.height = (int32_t)s.height;
         a.pitch = s.pitch;
         a.k = kk;
+        a.halo = kk;
         a.core_x = g.core_x;
         a.core_y = g.core_y;
         a.tiles_x = g.tiles_x;
@@ -487,6 +492,418 @@ static int run_reconstruct(gc_dtype dtype, int op, const void *marker, const voi
     if (steps_out) *steps_out = total;
     if (!converged) return fail(GC_ERR_NOT_CONVERGED, "reconstruction did not converge in %lld steps",
                                 (long long)max_steps);
+    return GC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// persistent batched chains (plans)
+// ---------------------------------------------------------------------------
+struct PersistentFns {
+    const void *kernel;  // for the occupancy query
+    void (*launch)(const PersistentArgs &, int grid, hipStream_t);
+    int threads;
+};
+
+template <typename T, int OP, int MODE, int FAM>
+static void launch_persistent(const PersistentArgs &a, int grid, hipStream_t st) {
+    using F = Family<T, FAM>;
+    hipLaunchKernelGGL((persistent_chain_kernel<T, OP, MODE, F::CW, F::RPW, F::NW>), dim3(grid),
+                       dim3(64 * F::NW), 0, st, a);
+}
+
+template <typename T, int OP, int MODE, int FAM>
+static PersistentFns persistent_fns_t() {
+    using F = Family<T, FAM>;
+    PersistentFns f;
+    f.kernel = (const void *)&persistent_chain_kernel<T, OP, MODE, F::CW, F::RPW, F::NW>;
+    f.launch = &launch_persistent<T, OP, MODE, FAM>;
+    f.threads = 64 * F::NW;
+    return f;
+}
+
+template <typename T, int OP, int MODE>
+static PersistentFns persistent_fns_m(int fam) {
+    return fam == FAM_128 ? persistent_fns_t<T, OP, MODE, FAM_128>() : persistent_fns_t<T, OP, MODE, FAM_64>();
+}
+
+template <typename T>
+static PersistentFns persistent_fns_d(int op, int mode, int fam) {
+    if (op == OP_DILATE)
+        return mode == MODE_GEODESIC ? persistent_fns_m<T, OP_DILATE, MODE_GEODESIC>(fam)
+                                     : persistent_fns_m<T, OP_DILATE, MODE_PLAIN>(fam);
+    return mode == MODE_GEODESIC ? persistent_fns_m<T, OP_ERODE, MODE_GEODESIC>(fam)
+                                 : persistent_fns_m<T, OP_ERODE, MODE_PLAIN>(fam);
+}
+
+static PersistentFns persistent_fns(gc_dtype d, int op, int mode, int fam) {
+    switch (d) {
+        case GC_U8: return persistent_fns_d<uint8_t>(op, mode, fam);
+        case GC_F32: return persistent_fns_d<float>(op, mode, fam);
+        case GC_F64: return persistent_fns_d<double>(op, mode, fam);
+    }
+    return PersistentFns{};
+}
+
+// Largest steps per block the persistent kernel accepts: the halo must not
+// reach past the neighbouring tiles (k <= core = side - 2k).
+static int persistent_kmax(int fam) { return region_side(fam) / 3; }
+static int default_persistent_k(int fam) { return fam == FAM_128 ? 32 : 16; }
+
+// ---- autotuner table ----
+struct TuneKey {
+    int dtype, op, geodesic, cw, ch;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(dtype, op, geodesic, cw, ch) < std::tie(o.dtype, o.op, o.geodesic, o.cw, o.ch);
+    }
+};
+struct TuneVal {
+    int best_fam = FAM_128;
+    int k[NUM_FAMS] = {0, 0};
+    double rate[NUM_FAMS] = {0, 0};  // pixel-steps per second
+};
+static std::mutex g_autotune_mu;
+static std::map<TuneKey, TuneVal> g_autotune;
+
+static int ceil_log2(int64_t v) {
+    int c = 0;
+    while ((int64_t(1) << c) < v) ++c;
+    return c;
+}
+
+static TuneKey tune_key(gc_dtype d, int op, int geodesic, int64_t w, int64_t h) {
+    return TuneKey{(int)d, op, geodesic ? 1 : 0, ceil_log2(std::max<int64_t>(w, 1)),
+                   ceil_log2(std::max<int64_t>(h, 1))};
+}
+
+}  // namespace geochain
+
+struct gc_plan {
+    int device = 0;
+    gc_dtype dtype = GC_U8;
+    int op = 0, mode = 0, fam = 0, max_k = 0;
+    int32_t n_items = 0, grid = 0;
+    int64_t px_steps = 0;
+    std::vector<gc_item> items;
+    geochain::PlanImage *images_d = nullptr;
+    geochain::PlanItem *items_d = nullptr;
+    uint32_t *words_d = nullptr;  // [0] counter, [1] error, [2..] tile counters
+    int64_t n_words = 0;
+    void *ws = nullptr;
+    uint32_t *error_h = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool launched = false;
+};
+
+namespace geochain {
+
+static void plan_free(gc_plan *p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    if (p->images_d) (void)hipFree(p->images_d);
+    if (p->items_d) (void)hipFree(p->items_d);
+    if (p->words_d) (void)hipFree(p->words_d);
+    if (p->ws) (void)hipFree(p->ws);
+    if (p->error_h) (void)hipHostFree(p->error_h);
+    delete p;
+}
+
+struct PlanChoice {
+    int fam;
+    std::vector<int> k;  // per item
+};
+
+// Tile family for the whole plan and steps per block for each item: from
+// the autotuner when every item's size class has an entry, else built-in.
+static PlanChoice choose_plan_batch(gc_dtype d, int op, int mode, const std::vector<gc_item> &items) {
+    PlanChoice c;
+    c.fam = FAM_128;
+    int forced_k = 0, forced_fam = -1;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        forced_k = g_tune_k;
+        forced_fam = g_tune_tile;
+    }
+    std::vector<TuneVal> vals;
+    bool all_tuned = true;
+    {
+        std::lock_guard<std::mutex> g(g_autotune_mu);
+        for (const auto &it : items) {
+            auto f = g_autotune.find(tune_key(d, op, mode == MODE_GEODESIC, it.shape.width, it.shape.height));
+            if (f == g_autotune.end()) {
+                all_tuned = false;
+                vals.push_back(TuneVal{});
+            } else {
+                vals.push_back(f->second);
+            }
+        }
+    }
+    if (all_tuned && !items.empty()) {
+        double best_t = 1e300;
+        for (int fam = 0; fam < NUM_FAMS; ++fam) {
+            double t = 0;
+            bool ok = true;
+            for (size_t i = 0; i < items.size(); ++i) {
+                if (vals[i].rate[fam] <= 0) { ok = false; break; }
+                t += (double)items[i].shape.width * items[i].shape.height * items[i].n_steps / vals[i].rate[fam];
+            }
+            if (ok && t < best_t) { best_t = t; c.fam = fam; }
+        }
+    }
+    if (forced_fam >= 0) c.fam = forced_fam;
+    for (size_t i = 0; i < items.size(); ++i) {
+        int k = default_persistent_k(c.fam);
+        if (all_tuned && vals[i].k[c.fam] > 0) k = vals[i].k[c.fam];
+        if (forced_k > 0) k = forced_k;
+        k = std::max(1, std::min(k, persistent_kmax(c.fam)));
+        if (items[i].n_steps > 0 && items[i].n_steps < k) k = (int)items[i].n_steps;
+        c.k.push_back(k);
+    }
+    return c;
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+static int plan_build(gc_dtype dtype, int op, const gc_item *items, int32_t n_items, gc_plan **out,
+                      const PlanChoice *forced) {
+    if (!out) return fail(GC_ERR_INVALID_ARG, "plan_out is NULL");
+    *out = nullptr;
+    if (elem_size(dtype) == 0) return fail(GC_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+    if (op != OP_DILATE && op != OP_ERODE) return fail(GC_ERR_INVALID_ARG, "unknown op %d", op);
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(GC_ERR_INVALID_ARG, "bad item array");
+    int mode = -1;
+    for (int32_t i = 0; i < n_items; ++i) {
+        const gc_item &it = items[i];
+        int rc = validate_images(dtype, it.marker, it.mask, it.out, it.shape);
+        if (rc != GC_OK) return fail(rc, "item %d: %s", i, g_last_error.c_str());
+        if (it.n_steps < 0) return fail(GC_ERR_UNSUPPORTED, "item %d: n_steps < 0", i);
+        if (it.n_steps > INT32_MAX / 2) return fail(GC_ERR_UNSUPPORTED, "item %d: n_steps too large", i);
+        const bool empty = it.shape.width == 0 || it.shape.height == 0;
+        if (empty) continue;
+        const int m = it.mask ? MODE_GEODESIC : MODE_PLAIN;
+        if (mode >= 0 && m != mode)
+            return fail(GC_ERR_UNSUPPORTED, "a plan is either all geodesic or all plain (item %d)", i);
+        mode = m;
+    }
+    if (mode < 0) mode = MODE_GEODESIC;
+    const size_t es = elem_size(dtype);
+
+    gc_plan *p = new gc_plan();
+    p->dtype = dtype;
+    p->op = op;
+    p->mode = mode;
+    p->items.assign(items, items + n_items);
+    GC_HIP(hipGetDevice(&p->device));
+
+    const PlanChoice choice = forced ? *forced : choose_plan_batch(dtype, op, mode, p->items);
+    p->fam = choice.fam;
+    const int side = region_side(p->fam);
+
+    // ---- per-image descriptors, workspace layout, item list ----
+    std::vector<PlanImage> imgs;
+    std::vector<int> img_of_item;  // plan image index -> gc_item index
+    size_t ws_bytes = 0;
+    std::vector<size_t> ws_off;
+    int32_t flags = 0;
+    std::vector<std::pair<int, int>> copies;  // (gc_item index, kind) 0: n=0 copy, 1: marker->ws1
+    for (int32_t i = 0; i < n_items; ++i) {
+        const gc_item &it = p->items[i];
+        if (it.shape.width == 0 || it.shape.height == 0) continue;
+        if (it.n_steps == 0) { copies.push_back({i, 0}); continue; }
+        PlanImage im{};
+        im.marker = it.marker;
+        im.mask = it.mask;
+        im.out = it.out;
+        im.pitch = it.shape.pitch;
+        im.width = (int32_t)it.shape.width;
+        im.height = (int32_t)it.shape.height;
+        im.n_steps = (int32_t)it.n_steps;
+        im.k = choice.k[i];
+        im.core_x = side - 2 * im.k;
+        im.core_y = side - 2 * im.k;
+        im.tiles_x = (int32_t)((it.shape.width + im.core_x - 1) / im.core_x);
+        im.tiles_y = (int32_t)((it.shape.height + im.core_y - 1) / im.core_y);
+        im.blocks = (int32_t)((it.n_steps + im.k - 1) / im.k);
+        im.flag_base = flags;
+        flags += im.tiles_x * im.tiles_y;
+        im.src0_ws1 = (it.out == it.marker && im.blocks == 1) ? 1 : 0;
+        if (im.src0_ws1) copies.push_back({i, 1});
+        const size_t bytes = (size_t)((it.shape.height - 1) * it.shape.pitch + it.shape.width) * es;
+        const size_t aligned = (bytes + 255) & ~size_t(255);
+        ws_off.push_back(ws_bytes);
+        ws_bytes += 2 * aligned;
+        imgs.push_back(im);
+        img_of_item.push_back(i);
+        p->px_steps += it.shape.width * it.shape.height * it.n_steps;
+        p->max_k = std::max(p->max_k, im.k);
+    }
+    // items ordered by block, longest chains first within a block
+    std::vector<int> order(imgs.size());
+    for (size_t j = 0; j < order.size(); ++j) order[j] = (int)j;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (int64_t)imgs[a].blocks * imgs[a].k > (int64_t)imgs[b].blocks * imgs[b].k;
+    });
+    int max_blocks = 0;
+    for (auto &im : imgs) max_blocks = std::max(max_blocks, im.blocks);
+    std::vector<PlanItem> plan_items;
+    for (int b = 0; b < max_blocks; ++b)
+        for (int j : order) {
+            if (b >= imgs[j].blocks) continue;
+            const int nt = imgs[j].tiles_x * imgs[j].tiles_y;
+            for (int t = 0; t < nt; ++t) plan_items.push_back(PlanItem{j, t, b, 0});
+        }
+    p->n_items = (int32_t)plan_items.size();
+
+    // ---- device allocations ----
+    auto bail = [&](int rc) { plan_free(p); return rc; };
+    if (!imgs.empty()) {
+        if (hipMalloc(&p->ws, ws_bytes) != hipSuccess) { (void)hipGetLastError(); return bail(fail(GC_ERR_NO_MEMORY, "plan workspace of %zu bytes", ws_bytes)); }
+        for (size_t j = 0; j < imgs.size(); ++j) {
+            const gc_item &it = p->items[img_of_item[j]];
+            const size_t bytes = (size_t)((it.shape.height - 1) * it.shape.pitch + it.shape.width) * es;
+            const size_t aligned = (bytes + 255) & ~size_t(255);
+            imgs[j].ws0 = (char *)p->ws + ws_off[j];
+            imgs[j].ws1 = (char *)p->ws + ws_off[j] + aligned;
+        }
+        if (hipMalloc((void **)&p->images_d, imgs.size() * sizeof(PlanImage)) != hipSuccess ||
+            hipMalloc((void **)&p->items_d, std::max<size_t>(plan_items.size(), 1) * sizeof(PlanItem)) != hipSuccess) {
+            (void)hipGetLastError();
+            return bail(fail(GC_ERR_NO_MEMORY, "plan tables"));
+        }
+        if (hipMemcpy(p->images_d, imgs.data(), imgs.size() * sizeof(PlanImage), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(p->items_d, plan_items.data(), plan_items.size() * sizeof(PlanItem), hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(GC_ERR_HIP, "uploading plan tables"));
+    }
+    p->n_words = 2 + (int64_t)flags;
+    if (hipMalloc((void **)&p->words_d, p->n_words * 4) != hipSuccess ||
+        hipHostMalloc((void **)&p->error_h, 4, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(fail(GC_ERR_NO_MEMORY, "plan counters"));
+    }
+    *p->error_h = 0;
+
+    // ---- grid: as many workgroups as fit on the device at once ----
+    const PersistentFns fns = persistent_fns(dtype, op, mode, p->fam);
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fns.kernel, fns.threads, 0) != hipSuccess)
+        return bail(fail(GC_ERR_HIP, "occupancy query failed"));
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess)
+        return bail(fail(GC_ERR_HIP, "CU count query failed"));
+    p->grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>((int64_t)std::max(per_cu, 1) * cus,
+                                                               std::max<int32_t>(p->n_items, 1)));
+
+    // ---- record the launch ----
+    if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(GC_ERR_HIP, "stream creation failed"));
+    if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return bail(fail(GC_ERR_HIP, "graph capture failed to start"));
+    bool cap_ok = true;
+    // Counters start at zero: a fill kernel, not a memset node.
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)std::min<int64_t>((p->n_words + 255) / 256, 1024)), dim3(256), 0,
+                       p->cap_stream, p->words_d, p->n_words, 0u);
+    cap_ok = cap_ok && hipGetLastError() == hipSuccess;
+    for (auto &c : copies) {
+        const gc_item &it = p->items[c.first];
+        void *dst = it.out;
+        if (c.second == 1) {
+            for (size_t j = 0; j < imgs.size(); ++j)
+                if (img_of_item[j] == c.first) dst = imgs[j].ws1;
+        }
+        if (dst != it.marker)
+            cap_ok = cap_ok && hipMemcpy2DAsync(dst, it.shape.pitch * es, it.marker, it.shape.pitch * es,
+                                                it.shape.width * es, it.shape.height, hipMemcpyDeviceToDevice,
+                                                p->cap_stream) == hipSuccess;
+    }
+    if (p->n_items > 0) {
+        PersistentArgs a{};
+        a.images = p->images_d;
+        a.items = p->items_d;
+        a.n_items = p->n_items;
+        a.counter = p->words_d;
+        a.error = p->words_d + 1;
+        a.flags = p->words_d + 2;
+        a.spin_limit = 1u << 18;
+        fns.launch(a, p->grid, p->cap_stream);
+        cap_ok = cap_ok && hipGetLastError() == hipSuccess;
+        // Error word to pinned host memory for gc_plan_status.
+        cap_ok = cap_ok && hipMemcpyAsync(p->error_h, p->words_d + 1, 4, hipMemcpyDeviceToHost, p->cap_stream) == hipSuccess;
+    }
+    hipError_t ec = hipStreamEndCapture(p->cap_stream, &p->graph);
+    if (ec != hipSuccess || !cap_ok) return bail(fail(GC_ERR_HIP, "graph capture failed: %s", hipGetErrorString(ec)));
+    if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+        return bail(fail(GC_ERR_HIP, "graph instantiation failed"));
+    *out = p;
+    return GC_OK;
+}
+
+static int plan_time(gc_plan *p, int reps, double *ms_out) {
+    hipStream_t st = p->cap_stream;
+    hipEvent_t a, b;
+    GC_HIP(hipEventCreate(&a));
+    GC_HIP(hipEventCreate(&b));
+    GC_HIP(hipGraphLaunch(p->exec, st));  // warm-up
+    GC_HIP(hipEventRecord(a, st));
+    for (int i = 0; i < reps; ++i) GC_HIP(hipGraphLaunch(p->exec, st));
+    GC_HIP(hipEventRecord(b, st));
+    GC_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    GC_HIP(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms_out = ms / reps;
+    return *p->error_h ? fail(GC_ERR_HIP, "dependency wait hit its bound while tuning") : GC_OK;
+}
+
+static int autotune(gc_dtype dtype, int op, int geodesic, int64_t width, int64_t height, TuneVal *out) {
+    const size_t es = elem_size(dtype);
+    // Enough copies of the size class to fill the device, as in a batch.
+    const int64_t px = std::max<int64_t>(width * height, 1);
+    const int copies = (int)std::max<int64_t>(1, std::min<int64_t>(64, (2048LL * 2048LL + px - 1) / px));
+    const size_t bytes = (size_t)(width * height) * es;
+    void *buf = nullptr;
+    if (hipMalloc(&buf, std::max<size_t>(bytes, 1) * 3 * copies) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GC_ERR_NO_MEMORY, "autotune scratch");
+    }
+    GC_HIP(hipMemset(buf, 0, std::max<size_t>(bytes, 1) * 3 * copies));
+    const int n_steps = 240;
+    TuneVal tv;
+    double best_rate = 0;
+    for (int fam = 0; fam < NUM_FAMS; ++fam) {
+        for (int k = 4; k <= persistent_kmax(fam); k += 4) {
+            std::vector<gc_item> items(copies);
+            for (int c = 0; c < copies; ++c) {
+                char *base = (char *)buf + (size_t)c * 3 * bytes;
+                items[c].marker = base;
+                items[c].mask = geodesic ? base + bytes : nullptr;
+                items[c].out = base + 2 * bytes;
+                items[c].shape = gc_shape{width, height, width};
+                items[c].n_steps = n_steps;
+            }
+            PlanChoice ch;
+            ch.fam = fam;
+            ch.k.assign(copies, k);
+            gc_plan *p = nullptr;
+            int rc = plan_build(dtype, op, items.data(), copies, &p, &ch);
+            if (rc != GC_OK) { (void)hipFree(buf); return rc; }
+            double ms = 0;
+            rc = plan_time(p, 3, &ms);
+            plan_free(p);
+            if (rc != GC_OK) { (void)hipFree(buf); return rc; }
+            const double rate = (double)px * copies * n_steps / (ms * 1e-3);
+            if (rate > tv.rate[fam]) { tv.rate[fam] = rate; tv.k[fam] = k; }
+            if (rate > best_rate) { best_rate = rate; tv.best_fam = fam; }
+        }
+    }
+    (void)hipFree(buf);
+    *out = tv;
     return GC_OK;
 }
 
@@ -573,6 +990,81 @@ int gc_reconstruct_by_erosion(gc_dtype dtype, const void *marker, const void *ma
                               gc_shape shape, int64_t max_steps, int64_t *steps_out,
                               void *hip_stream) {
     return reconstruct(dtype, OP_ERODE, marker, mask, out, shape, max_steps, steps_out, hip_stream);
+}
+
+int gc_plan_create(gc_dtype dtype, gc_op op, const gc_item *items, int32_t n_items, gc_plan **plan_out) {
+    g_last_error.clear();
+    return plan_build(dtype, (int)op, items, n_items, plan_out, nullptr);
+}
+
+int gc_plan_launch(gc_plan *plan, void *hip_stream) {
+    g_last_error.clear();
+    if (!plan) return fail(GC_ERR_INVALID_ARG, "plan is NULL");
+    int dev = 0;
+    GC_HIP(hipGetDevice(&dev));
+    if (dev != plan->device) return fail(GC_ERR_INVALID_ARG, "plan belongs to device %d", plan->device);
+    const int pr = prof_begin((hipStream_t)hip_stream, 0);
+    GC_HIP(hipGraphLaunch(plan->exec, (hipStream_t)hip_stream));
+    prof_end(pr, (hipStream_t)hip_stream);
+    plan->last_stream = (hipStream_t)hip_stream;
+    plan->launched = true;
+    return GC_OK;
+}
+
+int gc_plan_status(gc_plan *plan) {
+    g_last_error.clear();
+    if (!plan) return fail(GC_ERR_INVALID_ARG, "plan is NULL");
+    if (!plan->launched) return GC_OK;
+    GC_HIP(hipStreamSynchronize(plan->last_stream));
+    if (*plan->error_h) return fail(GC_ERR_HIP, "a dependency wait inside the batch kernel hit its bound");
+    return GC_OK;
+}
+
+int gc_plan_info(const gc_plan *plan, int64_t *px_steps, int64_t *work_items, int32_t *workgroups,
+                 int32_t *tile, int32_t *block_steps) {
+    g_last_error.clear();
+    if (!plan) return fail(GC_ERR_INVALID_ARG, "plan is NULL");
+    if (px_steps) *px_steps = plan->px_steps;
+    if (work_items) *work_items = plan->n_items;
+    if (workgroups) *workgroups = plan->grid;
+    if (tile) *tile = plan->fam;
+    if (block_steps) *block_steps = plan->max_k;
+    return GC_OK;
+}
+
+int gc_plan_destroy(gc_plan *plan) {
+    g_last_error.clear();
+    if (!plan) return GC_OK;
+    if (plan->launched) (void)hipStreamSynchronize(plan->last_stream);
+    plan_free(plan);
+    return GC_OK;
+}
+
+int gc_autotune(gc_dtype dtype, gc_op op, int32_t geodesic, int64_t width, int64_t height, int32_t *best_tile,
+                int32_t *best_k) {
+    g_last_error.clear();
+    if (elem_size(dtype) == 0) return fail(GC_ERR_INVALID_ARG, "unknown dtype");
+    if (op != GC_DILATE && op != GC_ERODE) return fail(GC_ERR_INVALID_ARG, "unknown op");
+    if (width < 1 || height < 1 || width > 16384 || height > 16384)
+        return fail(GC_ERR_INVALID_ARG, "tuning sizes are 1..16384");
+    // Tune on the size class's upper corner.
+    const TuneKey key = tune_key(dtype, (int)op, geodesic, width, height);
+    TuneVal tv;
+    int rc = autotune(dtype, (int)op, geodesic, int64_t(1) << key.cw, int64_t(1) << key.ch, &tv);
+    if (rc != GC_OK) return rc;
+    {
+        std::lock_guard<std::mutex> g(g_autotune_mu);
+        g_autotune[key] = tv;
+    }
+    if (best_tile) *best_tile = tv.best_fam;
+    if (best_k) *best_k = tv.k[tv.best_fam];
+    return GC_OK;
+}
+
+int gc_autotune_clear(void) {
+    std::lock_guard<std::mutex> g(g_autotune_mu);
+    g_autotune.clear();
+    return GC_OK;
 }
 
 int gc_profile_enable(int on) {

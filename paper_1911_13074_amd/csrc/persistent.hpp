@@ -1,0 +1,154 @@
+// persistent.hpp -- one persistent launch that runs many chains (a batch of
+// images with their own sizes and chain lengths) to completion.
+//
+// Work is cut into items (image, tile, block): block b of a tile advances its
+// core from step b*k to step min((b+1)*k, n) with the same register-resident
+// body as the per-launch kernel (chain_block.hpp).  Items sit in one global
+// list ordered by block index, so the list is a valid topological order of
+// the dependencies below.  Workgroups take items in list order from an atomic
+// counter and, before loading, wait until the item's 3x3 neighbourhood of
+// tiles has finished block b-1 (a per-tile counter, released after the
+// tile's stores).  This is the GPU counterpart of the paper's per-filter row
+// counters with acquire/release semantics (Section 3.5): here the counters
+// are per tile and per block of k steps instead of per row and per step.
+//
+// Progress: an item only waits for items earlier in the list, and every
+// earlier item was taken by a workgroup that is already running, so the
+// earliest unfinished item can always proceed; no co-residency of the whole
+// grid is assumed.  Every wait is bounded: past spin_limit polls the item
+// sets the error word and goes on, so the launch always drains.
+//
+// Buffers: block b reads state from marker (b = 0) or ws[(b-1)&1] and writes
+// ws[b&1], except the last block which writes out.  A tile's block b may
+// overwrite ws[b&1] only after its neighbours finished block b-1, which was
+// the last reader of that buffer, so the same counters also order the
+// write-after-read reuse of the two work buffers.
+#pragma once
+
+#include "chain_block.hpp"
+
+namespace geochain {
+
+struct PlanImage {
+    const void *marker;
+    const void *mask;
+    void *out;
+    void *ws0;
+    void *ws1;
+    int64_t pitch;
+    int32_t width, height;
+    int32_t n_steps;
+    int32_t k;          // steps per block (the last block may be shorter)
+    int32_t core_x, core_y;
+    int32_t tiles_x, tiles_y;
+    int32_t blocks;
+    int32_t flag_base;  // first per-tile counter of this image
+    int32_t src0_ws1;   // block 0 reads ws1 (in-place single-block chains)
+    int32_t pad;
+};
+
+struct PlanItem {
+    int32_t image;
+    int32_t tile;
+    int32_t block;
+    int32_t pad;
+};
+
+struct PersistentArgs {
+    const PlanImage *images;
+    const PlanItem *items;
+    int32_t n_items;
+    uint32_t *counter;   // next item to take
+    uint32_t *flags;     // per tile: number of blocks finished
+    uint32_t *error;     // bit 0: a wait hit spin_limit
+    uint32_t spin_limit;
+};
+
+// Waits until every tile of the 3x3 neighbourhood of (tx, ty) has finished
+// at least `need` blocks.  Called by one whole wave; lane j < 9 watches
+// neighbour j.  Returns false if the wait hit spin_limit.
+__device__ __forceinline__ bool wait_neighbours(const PersistentArgs &a, const PlanImage &im, int tx, int ty,
+                                                uint32_t need) {
+    const int lane = threadIdx.x & 63;
+    const int dy = lane / 3 - 1, dx = lane % 3 - 1;
+    const int nx = tx + dx, ny = ty + dy;
+    const bool mine = lane < 9 && nx >= 0 && nx < im.tiles_x && ny >= 0 && ny < im.tiles_y;
+    const uint32_t *flag = a.flags + im.flag_base + (mine ? ny * im.tiles_x + nx : 0);
+    uint32_t polls = 0;
+    bool done = false;
+    while (!done && polls <= a.spin_limit) {
+        bool ok = true;
+        if (mine) ok = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
+        done = __builtin_amdgcn_ballot_w64(!ok) == 0;
+        if (!done) __builtin_amdgcn_s_sleep(2);
+        ++polls;
+    }
+    return done;
+}
+
+template <typename T, int OP, int MODE, int CW, int RPW, int NW>
+__global__ __launch_bounds__(64 * NW) void persistent_chain_kernel(PersistentArgs a) {
+    using R = typename RegOf<T>::type;
+    __shared__ R xch[2][NW][2][64 * CW];
+    __shared__ int s_item;
+
+    const int tid = threadIdx.x;
+    // Control flow below stays uniform across the workgroup: the loop
+    // condition comes from LDS through readfirstlane, and the one-lane
+    // sections are closed by a barrier before anything reads their result.
+    if (tid == 0) s_item = (int)atomicAdd(a.counter, 1u);
+    __syncthreads();
+    int it = __builtin_amdgcn_readfirstlane(s_item);
+    while (it < a.n_items) {
+        const PlanItem item = a.items[it];
+        const PlanImage &im = a.images[item.image];
+        const int tx = item.tile % im.tiles_x;
+        const int ty = item.tile / im.tiles_x;
+        const int b = item.block;
+
+        // ---- wait for the 3x3 neighbourhood to finish block b-1 ----
+        // Once any wait has failed the results are void anyway: stop waiting
+        // so the launch drains quickly.
+        if (b > 0 && tid < 64 &&
+            __hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            const bool ok = wait_neighbours(a, im, tx, ty, (uint32_t)b);
+            if (!ok && tid == 0) atomicOr(a.error, 1u);
+        }
+        __syncthreads();
+        // Make the neighbours' stores visible to this workgroup's loads.
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+
+        // ---- the block itself ----
+        const int k_b = (b == im.blocks - 1) ? im.n_steps - b * im.k : im.k;
+        BlockArgs ba{};
+        ba.src = b == 0 ? (im.src0_ws1 ? (const void *)im.ws1 : im.marker)
+                        : (const void *)((b - 1) & 1 ? im.ws1 : im.ws0);
+        ba.mask = im.mask;
+        ba.dst = b == im.blocks - 1 ? im.out : (b & 1 ? im.ws1 : im.ws0);
+        ba.width = im.width;
+        ba.height = im.height;
+        ba.pitch = im.pitch;
+        ba.k = k_b;
+        ba.halo = im.k;
+        ba.core_x = im.core_x;
+        ba.core_y = im.core_y;
+        ba.tiles_x = im.tiles_x;
+        const int rx0 = tx * im.core_x - im.k;
+        const int ry0 = ty * im.core_y - im.k;
+        chain_block_dispatch<T, OP, MODE, false, CW, RPW, NW>(ba, rx0, ry0, xch);
+
+        // ---- publish: stores first, then the tile's counter; take the next item ----
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __syncthreads();
+        if (tid == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_store(a.flags + im.flag_base + item.tile, (uint32_t)(b + 1), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            s_item = (int)atomicAdd(a.counter, 1u);
+        }
+        __syncthreads();
+        it = __builtin_amdgcn_readfirstlane(s_item);
+    }
+}
+
+}  // namespace geochain

@@ -139,3 +139,92 @@ def reconstruct_by_erosion(marker, mask, max_steps=-1, out=None, allow_not_conve
 def set_tuning(block_steps: int = 0, tile: int = -1) -> None:
     """Override steps per launch and tile family (0 / -1: built-in choice)."""
     abi.check(abi.gc_set_tuning(int(block_steps), int(tile)), "gc_set_tuning")
+
+
+class BatchPlan:
+    """Many independent chains in one persistent, graph-recorded launch.
+
+    items: sequence of (marker, mask_or_None, n_steps) or (marker, mask,
+    n_steps, out).  All images share one dtype and device; all items are
+    geodesic (mask given) or all plain.  The outputs are allocated here when
+    not given.  launch() replays the recorded graph on the current stream.
+    """
+
+    def __init__(self, op, items):
+        if op not in ("dilate", "erode"):
+            raise ValueError("op is 'dilate' or 'erode'")
+        self._plan = None
+        self.outs = []
+        self._keep = []
+        arr = (abi.gc_item * max(len(items), 1))()
+        dtype = None
+        self.device = None
+        for i, it in enumerate(items):
+            marker, mask, n = it[0], it[1], int(it[2])
+            out = it[3] if len(it) > 3 else None
+            _check_image(marker, "marker")
+            if mask is not None:
+                _check_image(mask, "mask")
+                _same_layout(marker, mask, "marker/mask")
+            out = _out_like(marker, out)
+            if dtype is None:
+                dtype, self.device = marker.dtype, marker.device
+            elif marker.dtype != dtype or marker.device != self.device:
+                raise ValueError("all items share one dtype and device")
+            self.outs.append(out)
+            self._keep += [marker, mask]
+            arr[i].marker = marker.data_ptr()
+            arr[i].mask = mask.data_ptr() if mask is not None else None
+            arr[i].out = out.data_ptr()
+            arr[i].shape = _shape(marker)
+            arr[i].n_steps = n
+        self.dtype = dtype if dtype is not None else torch.uint8
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device if self.device is not None else torch.cuda.current_device()):
+            st = abi.gc_plan_create(_DTYPES[self.dtype], abi.GC_DILATE if op == "dilate" else abi.GC_ERODE,
+                                    arr, len(items), ctypes.byref(handle))
+        abi.check(st, "gc_plan_create")
+        self._plan = handle
+
+    def launch(self):
+        dev = self.device if self.device is not None else torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(dev):
+            stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+            abi.check(abi.gc_plan_launch(self._plan, stream), "gc_plan_launch")
+        return self.outs
+
+    def status(self):
+        abi.check(abi.gc_plan_status(self._plan), "gc_plan_status")
+
+    def info(self):
+        px, items = ctypes.c_int64(), ctypes.c_int64()
+        wgs, tile, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        abi.check(abi.gc_plan_info(self._plan, ctypes.byref(px), ctypes.byref(items), ctypes.byref(wgs),
+                                   ctypes.byref(tile), ctypes.byref(k)), "gc_plan_info")
+        return {"px_steps": px.value, "work_items": items.value, "workgroups": wgs.value,
+                "tile": tile.value, "block_steps": k.value}
+
+    def close(self):
+        if self._plan is not None:
+            abi.gc_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(dtype, op, geodesic, width, height):
+    """Time the batch kernel's launch shapes for a size class; the choice
+    is used by later plans.  Returns (tile_family, steps_per_block)."""
+    code = _DTYPES[dtype] if isinstance(dtype, torch.dtype) else int(dtype)
+    tile, k = ctypes.c_int32(), ctypes.c_int32()
+    abi.check(abi.gc_autotune(code, abi.GC_DILATE if op == "dilate" else abi.GC_ERODE, int(bool(geodesic)),
+                              int(width), int(height), ctypes.byref(tile), ctypes.byref(k)), "gc_autotune")
+    return tile.value, k.value
+
+
+def autotune_clear():
+    abi.check(abi.gc_autotune_clear(), "gc_autotune_clear")
