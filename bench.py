@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--size", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="headline chain only")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB, 5 times "
+                         "(reference dispatch for HBM byte counters), then exit")
     return ap.parse_args()
 
 
@@ -80,6 +83,34 @@ def kernel_profile(fn, steps):
     return ms.value / max(n.value, 1), n.value, st.value
 
 
+PROFILE = os.path.join(ROOT, "profiles", "chain_u8_1024_geodesic_dilation.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1911_13074_amd", "csrc", "chain_block.hpp")]
+
+
+def profiled_traffic():
+    """HBM bytes per dispatch of the chain kernel from the committed
+    rocprofv3 counter summary, or None if the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None, None
+    vals = {}
+    for line in text.splitlines():
+        line = line.strip()
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_dispatch", "kernel_source_sha256_16",
+                                                  "avg_dispatch_ns"):
+            k, v = line.split(":", 1)
+            vals[k] = v.strip()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    if vals.get("kernel_source_sha256_16") != h.hexdigest()[:16]:
+        return None, None
+    return int(vals["traffic_bytes_per_dispatch"]), float(vals["avg_dispatch_ns"]) * 1e-6
+
+
 def cpu_baseline(f, m, n_steps):
     import oracle
     threads = oracle.max_threads()
@@ -103,10 +134,20 @@ def main():
         print(f"bench.py measures one GPU: this build has no multi-GPU path "
               f"(asked for --gpus {args.gpus}).", file=sys.stderr)
         sys.exit(2)
-    import paper_1911_13074_amd as gc
-
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        n = args.copy_calibration << 20
+        a = torch.empty(n, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n, "copies": 5}), flush=True)
+        return
+    import paper_1911_13074_amd as gc
+
     N, S = args.chain, args.size
     f, m = workloads.headline_u8_dilation(size=S)
     F = torch.from_numpy(f).to(dev)
@@ -117,22 +158,32 @@ def main():
     def step():
         gc.geodesic_dilate_chain(F, M, N, out=out)
 
+    # launches per chain, counted by the library's launch hook (untimed)
+    _, launches, k_steps = kernel_profile(step, 1)
+
     ms = timed(step, args.steps, args.warmup)
     value = px * N / (ms * 1e-3) / 1e9
 
-    k_ms, launches, k_steps = kernel_profile(step, max(2, min(args.steps, 5)))
+    # The chain's launches run back to back on the launch stream (the kernel
+    # trace shows no gap between them), so the HIP-event time of the timed
+    # region divided by the launches in it is the kernel's average duration.
+    k_ms = ms / max(launches, 1)
     steps_per_launch = k_steps / max(launches, 1)
     achieved = CMP_PER_PX_STEP_GEODESIC * px * steps_per_launch / (k_ms * 1e-3) / 1e12
+    traffic, prof_ms = profiled_traffic()
     roofline = {
         "bound": "alu",
         "achieved": round(achieved, 3),
         "peak": round(PEAK_TCMP, 2),
         "unit": "Tcmp/s",
         "frac": round(achieved / PEAK_TCMP, 4),
-        "traffic": None,
+        "traffic": traffic,
         "kernel": "chain_block_kernel<u8, dilate, geodesic>",
         "avg_launch_ms": round(k_ms, 5),
+        "launches_per_step": launches,
         "steps_per_launch": round(steps_per_launch, 2),
+        "rocprof_avg_dispatch_ms": round(prof_ms, 5) if prof_ms else None,
+        "algorithmic_bytes_per_launch": 3 * px,
     }
 
     extra = {}
