@@ -186,6 +186,40 @@ int gc_autotune(gc_dtype dtype, gc_op op, int32_t geodesic, int64_t width, int64
 int gc_autotune_clear(void);
 
 /* ---------------------------------------------------------------------
+ * Differentiation of a geodesic chain (not in the paper).  f32 and f64
+ * only; values must be finite.
+ *
+ * Every output value of the chain is a copy of one input value (a marker
+ * pixel or a mask pixel), so the chain is piecewise the identity on a
+ * selection of its inputs.  gc_geodesic_chain_fwd_codes runs n_steps
+ * geodesic steps like gc_geodesic_{dilate,erode}_chain and also writes, for
+ * every step t and pixel p, a code naming where out_t(p) came from:
+ *   (dy+1)*3 + (dx+1)  the FIRST extremal neighbour (dx, dy in -1..1) of
+ *                      the clipped 3x3 window in raster (dy, dx) order;
+ *   9                  the mask won the clamp (ties go to the mask).
+ * codes: caller-owned device buffer of n_images * n_steps * height * width
+ * bytes, dense, index ((i * n_steps + t) * height + y) * width + x.
+ *
+ * gc_geodesic_chain_bwd takes those codes and the gradient w.r.t. the
+ * final state (grad_out) and WRITES grad_marker (gradient w.r.t. the state
+ * before step 0) and ADDS the mask's gradient into grad_mask.  Each pixel
+ * gathers the gradients of the neighbours whose codes point at it, visiting
+ * them in raster order (the same order in which a raster-order scatter
+ * would deliver them).  grad_marker must not overlap grad_out or grad_mask.
+ *
+ * Batches: n_images images of one shape, image i at element offset
+ * i * image_stride from each image pointer (image_stride >= (height - 1) *
+ * pitch + width when n_images > 1).  One kernel launch per step covers the
+ * whole batch.
+ * ------------------------------------------------------------------- */
+int gc_geodesic_chain_fwd_codes(gc_dtype dtype, gc_op op, const void *marker, const void *mask,
+                                void *out, uint8_t *codes, gc_shape shape, int32_t n_images,
+                                int64_t image_stride, int64_t n_steps, void *hip_stream);
+int gc_geodesic_chain_bwd(gc_dtype dtype, const uint8_t *codes, const void *grad_out,
+                          void *grad_marker, void *grad_mask, gc_shape shape, int32_t n_images,
+                          int64_t image_stride, int64_t n_steps, void *hip_stream);
+
+/* ---------------------------------------------------------------------
  * Tuning hook: override the temporal-block depth (steps fused per launch)
  * and the tile family used by the chain kernels.  block_steps = 0 and
  * tile = -1 restore the built-in choice.  Process-wide; intended for the

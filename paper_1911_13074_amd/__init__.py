@@ -6,12 +6,15 @@ include/geochain.h (libgeochain.so); this package only marshals torch
 tensors to it.
 """
 from .abi import GeochainError  # noqa: F401
+from .autograd import GeodesicChainFunction, geodesic_chain  # noqa: F401
 from .ops import (  # noqa: F401
     BatchPlan,
     autotune,
     autotune_clear,
     dilate_chain,
     erode_chain,
+    geodesic_chain_bwd,
+    geodesic_chain_fwd_codes,
     geodesic_dilate_chain,
     geodesic_erode_chain,
     reconstruct_by_dilation,

@@ -65,6 +65,9 @@ SIGNATURES = {
     "gc_autotune": (ctypes.c_int, [_DT, _DT, _I32, _I64, _I64, ctypes.POINTER(_I32),
                                    ctypes.POINTER(_I32)]),
     "gc_autotune_clear": (ctypes.c_int, []),
+    "gc_geodesic_chain_fwd_codes": (ctypes.c_int, [_DT, _DT, _VP, _VP, _VP, _VP, gc_shape, _I32, _I64,
+                                                   _I64, _VP]),
+    "gc_geodesic_chain_bwd": (ctypes.c_int, [_DT, _VP, _VP, _VP, _VP, gc_shape, _I32, _I64, _I64, _VP]),
     "gc_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "gc_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), _P_I64, _P_I64]),
 }

@@ -19,6 +19,7 @@
 #include "geochain.h"
 #include "chain_block.hpp"
 #include "persistent.hpp"
+#include "grad_step.hpp"
 
 namespace geochain {
 
@@ -907,6 +908,135 @@ static int autotune(gc_dtype dtype, int op, int geodesic, int64_t width, int64_t
     return GC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// differentiation: per-step codes and the reverse gather
+// ---------------------------------------------------------------------------
+static int validate_batch(gc_dtype dtype, const gc_shape &s, int32_t n_images, int64_t image_stride,
+                          int64_t n_steps) {
+    int rc = validate_shape(dtype, s);
+    if (rc != GC_OK) return rc;
+    if (dtype != GC_F32 && dtype != GC_F64) return fail(GC_ERR_UNSUPPORTED, "gradients need f32 or f64 images");
+    if (n_images < 0) return fail(GC_ERR_INVALID_ARG, "n_images < 0");
+    if (n_steps < 0) return fail(GC_ERR_INVALID_ARG, "n_steps < 0");
+    if (n_images > 65535) return fail(GC_ERR_UNSUPPORTED, "at most 65535 images per call");
+    const int64_t span = s.height > 0 ? (s.height - 1) * s.pitch + s.width : 0;
+    if (n_images > 1 && image_stride < span)
+        return fail(GC_ERR_INVALID_ARG, "image_stride %lld < image span %lld", (long long)image_stride,
+                    (long long)span);
+    return GC_OK;
+}
+
+// Byte extent of a batch of images.
+static std::pair<uintptr_t, uintptr_t> batch_extent(const void *p, const gc_shape &s, int32_t n, int64_t stride,
+                                                     size_t es) {
+    uintptr_t lo = (uintptr_t)p;
+    if (s.width == 0 || s.height == 0 || n == 0) return {lo, lo};
+    const uint64_t span = (uint64_t)(s.height - 1) * s.pitch + s.width;
+    return {lo, lo + ((uint64_t)(n - 1) * stride + span) * es};
+}
+
+static dim3 step_grid(const gc_shape &s, int32_t n_images) {
+    return dim3((unsigned)((s.width + GT_X - 1) / GT_X), (unsigned)((s.height + GT_Y - 1) / GT_Y),
+                (unsigned)n_images);
+}
+
+template <typename T>
+static void launch_codes(int op, const StepArgs &a, dim3 grid, hipStream_t st) {
+    if (op == OP_DILATE)
+        hipLaunchKernelGGL((step_codes_kernel<T, OP_DILATE>), grid, dim3(GT_THREADS), 0, st, a);
+    else
+        hipLaunchKernelGGL((step_codes_kernel<T, OP_ERODE>), grid, dim3(GT_THREADS), 0, st, a);
+}
+
+static int run_fwd_codes(gc_dtype dtype, int op, const void *marker, const void *mask, void *out, uint8_t *codes,
+                         const gc_shape &s, int32_t n, int64_t stride, int64_t n_steps, hipStream_t st) {
+    const size_t es = elem_size(dtype);
+    if (s.width == 0 || s.height == 0 || n == 0) return GC_OK;
+    const int64_t span = (s.height - 1) * s.pitch + s.width;
+    const int64_t istride = n > 1 ? stride : span;
+    const size_t batch_bytes = (size_t)((int64_t)(n - 1) * istride + span) * es;
+    if (n_steps == 0) {
+        if (out != marker)
+            GC_HIP(hipMemcpyAsync(out, marker, batch_bytes, hipMemcpyDeviceToDevice, st));
+        return GC_OK;
+    }
+    const size_t half = (batch_bytes + 255) & ~size_t(255);
+    Workspace *ws = nullptr;
+    int rc = get_workspace(st, 2 * half, 0, &ws);
+    if (rc != GC_OK) return rc;
+    void *w[2] = {ws->buf, (char *)ws->buf + half};
+    const void *cur = marker;
+    if (out == marker && n_steps == 1) {
+        GC_HIP(hipMemcpyAsync(w[1], marker, batch_bytes, hipMemcpyDeviceToDevice, st));
+        cur = w[1];
+    }
+    const int64_t codes_step = s.height * s.width;
+    const dim3 grid = step_grid(s, n);
+    for (int64_t t = 0; t < n_steps; ++t) {
+        void *dst = t == n_steps - 1 ? out : w[t & 1];
+        StepArgs a{};
+        a.src = cur;
+        a.mask = mask;
+        a.dst = dst;
+        a.codes = codes + t * codes_step;
+        a.codes_image_stride = n_steps * codes_step;
+        a.image_stride = istride;
+        a.pitch = s.pitch;
+        a.width = (int32_t)s.width;
+        a.height = (int32_t)s.height;
+        const int pr = prof_begin(st, 1);
+        if (dtype == GC_F32) launch_codes<float>(op, a, grid, st);
+        else launch_codes<double>(op, a, grid, st);
+        prof_end(pr, st);
+        GC_HIP(hipGetLastError());
+        cur = dst;
+    }
+    return GC_OK;
+}
+
+static int run_bwd(gc_dtype dtype, const uint8_t *codes, const void *g_out, void *g_marker, void *g_mask,
+                   const gc_shape &s, int32_t n, int64_t stride, int64_t n_steps, hipStream_t st) {
+    const size_t es = elem_size(dtype);
+    if (s.width == 0 || s.height == 0 || n == 0) return GC_OK;
+    const int64_t span = (s.height - 1) * s.pitch + s.width;
+    const int64_t istride = n > 1 ? stride : span;
+    const size_t batch_bytes = (size_t)((int64_t)(n - 1) * istride + span) * es;
+    if (n_steps == 0) {
+        GC_HIP(hipMemcpyAsync(g_marker, g_out, batch_bytes, hipMemcpyDeviceToDevice, st));
+        return GC_OK;
+    }
+    const size_t half = (batch_bytes + 255) & ~size_t(255);
+    Workspace *ws = nullptr;
+    int rc = get_workspace(st, 2 * half, 0, &ws);
+    if (rc != GC_OK) return rc;
+    void *w[2] = {ws->buf, (char *)ws->buf + half};
+    const int64_t codes_step = s.height * s.width;
+    const dim3 grid = step_grid(s, n);
+    const void *cur = g_out;
+    for (int64_t t = n_steps - 1; t >= 0; --t) {
+        void *dst = t == 0 ? g_marker : w[t & 1];
+        BwdArgs a{};
+        a.codes = codes + t * codes_step;
+        a.codes_image_stride = n_steps * codes_step;
+        a.g_in = cur;
+        a.g_out = dst;
+        a.g_mask = g_mask;
+        a.image_stride = istride;
+        a.pitch = s.pitch;
+        a.width = (int32_t)s.width;
+        a.height = (int32_t)s.height;
+        const int pr = prof_begin(st, 1);
+        if (dtype == GC_F32)
+            hipLaunchKernelGGL((step_bwd_kernel<float>), grid, dim3(GT_THREADS), 0, st, a);
+        else
+            hipLaunchKernelGGL((step_bwd_kernel<double>), grid, dim3(GT_THREADS), 0, st, a);
+        prof_end(pr, st);
+        GC_HIP(hipGetLastError());
+        cur = dst;
+    }
+    return GC_OK;
+}
+
 }  // namespace geochain
 
 using namespace geochain;
@@ -990,6 +1120,45 @@ int gc_reconstruct_by_erosion(gc_dtype dtype, const void *marker, const void *ma
                               gc_shape shape, int64_t max_steps, int64_t *steps_out,
                               void *hip_stream) {
     return reconstruct(dtype, OP_ERODE, marker, mask, out, shape, max_steps, steps_out, hip_stream);
+}
+
+int gc_geodesic_chain_fwd_codes(gc_dtype dtype, gc_op op, const void *marker, const void *mask, void *out,
+                                uint8_t *codes, gc_shape shape, int32_t n_images, int64_t image_stride,
+                                int64_t n_steps, void *hip_stream) {
+    g_last_error.clear();
+    int rc = validate_batch(dtype, shape, n_images, image_stride, n_steps);
+    if (rc != GC_OK) return rc;
+    if (op != GC_DILATE && op != GC_ERODE) return fail(GC_ERR_INVALID_ARG, "unknown op");
+    const bool empty = shape.width == 0 || shape.height == 0 || n_images == 0;
+    if (empty) return GC_OK;
+    if (!marker || !mask || !out || (n_steps > 0 && !codes)) return fail(GC_ERR_INVALID_ARG, "null pointer");
+    const size_t es = elem_size(dtype);
+    const auto eo = batch_extent(out, shape, n_images, image_stride, es);
+    if (overlap(eo, batch_extent(mask, shape, n_images, image_stride, es)))
+        return fail(GC_ERR_ALIAS, "out overlaps mask");
+    if (out != marker && overlap(eo, batch_extent(marker, shape, n_images, image_stride, es)))
+        return fail(GC_ERR_ALIAS, "out partially overlaps marker");
+    return run_fwd_codes(dtype, (int)op, marker, mask, out, codes, shape, n_images, image_stride, n_steps,
+                         (hipStream_t)hip_stream);
+}
+
+int gc_geodesic_chain_bwd(gc_dtype dtype, const uint8_t *codes, const void *grad_out, void *grad_marker,
+                          void *grad_mask, gc_shape shape, int32_t n_images, int64_t image_stride, int64_t n_steps,
+                          void *hip_stream) {
+    g_last_error.clear();
+    int rc = validate_batch(dtype, shape, n_images, image_stride, n_steps);
+    if (rc != GC_OK) return rc;
+    const bool empty = shape.width == 0 || shape.height == 0 || n_images == 0;
+    if (empty) return GC_OK;
+    if (!grad_out || !grad_marker || !grad_mask || (n_steps > 0 && !codes))
+        return fail(GC_ERR_INVALID_ARG, "null pointer");
+    const size_t es = elem_size(dtype);
+    const auto egm = batch_extent(grad_marker, shape, n_images, image_stride, es);
+    if (overlap(egm, batch_extent(grad_out, shape, n_images, image_stride, es)) ||
+        overlap(egm, batch_extent(grad_mask, shape, n_images, image_stride, es)))
+        return fail(GC_ERR_ALIAS, "grad_marker overlaps grad_out or grad_mask");
+    return run_bwd(dtype, codes, grad_out, grad_marker, grad_mask, shape, n_images, image_stride, n_steps,
+                   (hipStream_t)hip_stream);
 }
 
 int gc_plan_create(gc_dtype dtype, gc_op op, const gc_item *items, int32_t n_items, gc_plan **plan_out) {

@@ -228,3 +228,60 @@ def autotune(dtype, op, geodesic, width, height):
 
 def autotune_clear():
     abi.check(abi.gc_autotune_clear(), "gc_autotune_clear")
+
+
+def _batch_view(t: torch.Tensor, name: str):
+    """(B, H, W) or (H, W) device tensor -> (tensor, n_images, image_stride, shape)."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dim() == 2:
+        t3 = t.unsqueeze(0)
+    elif t.dim() == 3:
+        t3 = t
+    else:
+        raise ValueError(f"{name} must be (H, W) or (B, H, W)")
+    b, h, w = t3.shape
+    if w > 1 and t3.stride(2) != 1:
+        raise ValueError(f"{name} rows must be contiguous")
+    pitch = t3.stride(1) if h > 1 else max(w, 1)
+    stride = t3.stride(0) if b > 1 else (h - 1) * pitch + w if h > 0 else 0
+    return t3, b, stride, abi.gc_shape(w, h, max(pitch, w))
+
+
+def geodesic_chain_fwd_codes(op, marker, mask, n_steps, out=None, codes=None):
+    """n_steps geodesic steps that also record each pixel's source per step.
+
+    marker, mask: (H, W) or (B, H, W) float32/float64.  Returns (out, codes)
+    with codes of shape (B, n_steps, H, W) uint8 (B = 1 for 2-D inputs).
+    """
+    m3, b, stride, shape = _batch_view(marker, "marker")
+    k3, b2, stride2, shape2 = _batch_view(mask, "mask")
+    if (b, shape.width, shape.height, shape.pitch, stride) != (b2, shape2.width, shape2.height, shape2.pitch,
+                                                               stride2) or marker.dtype != mask.dtype:
+        raise ValueError("marker and mask layouts differ")
+    if out is None:
+        out = torch.empty_strided(marker.shape, marker.stride(), dtype=marker.dtype, device=marker.device)
+    if codes is None:
+        codes = torch.empty((b, int(n_steps), shape.height, shape.width), dtype=torch.uint8,
+                            device=marker.device)
+    with torch.cuda.device(marker.device):
+        st = abi.gc_geodesic_chain_fwd_codes(_dtype_code(marker), abi.GC_DILATE if op == "dilate" else abi.GC_ERODE,
+                                             _ptr(marker), _ptr(mask), _ptr(out), _ptr(codes), shape, b, stride,
+                                             int(n_steps), _stream(marker))
+    abi.check(st, "gc_geodesic_chain_fwd_codes")
+    return out, codes
+
+
+def geodesic_chain_bwd(codes, grad_out, grad_mask, grad_marker=None):
+    """Reverse pass over codes (B, n, H, W): returns the gradient w.r.t. the
+    state before the first step; adds the mask's gradient into grad_mask."""
+    g3, b, stride, shape = _batch_view(grad_out, "grad_out")
+    n_steps = codes.shape[1]
+    if grad_marker is None:
+        grad_marker = torch.empty_strided(grad_out.shape, grad_out.stride(), dtype=grad_out.dtype,
+                                          device=grad_out.device)
+    with torch.cuda.device(grad_out.device):
+        st = abi.gc_geodesic_chain_bwd(_dtype_code(grad_out), _ptr(codes), _ptr(grad_out), _ptr(grad_marker),
+                                       _ptr(grad_mask), shape, b, stride, int(n_steps), _stream(grad_out))
+    abi.check(st, "gc_geodesic_chain_bwd")
+    return grad_marker
