@@ -204,6 +204,42 @@ def main():
         extra["reconstruction_by_dilation"] = {
             "steps_changed": rec_steps["n"], "ms": round(ms_r, 4),
             "gpx_steps_per_s": round(px * rec_steps["n"] / ms_r / 1e6, 2)}
+        # Batched: 64 uneven images in one persistent graph-recorded launch.
+        batch = workloads.batch_u8()
+        items = [(torch.from_numpy(it.marker).to(dev), torch.from_numpy(it.mask).to(dev), it.n_steps)
+                 for it in batch.items]
+        plan = gc.BatchPlan("dilate", items)
+        ms_b = timed(plan.launch, max(3, args.steps // 4), 1)
+        plan.status()
+        info = plan.info()
+        rate_b = batch.px_steps / ms_b / 1e6
+        extra["batched_64_uneven_u8"] = {
+            "gpx_steps_per_s": round(rate_b, 2), "ms": round(ms_b, 3), "px_steps": batch.px_steps,
+            "vs_plain": round(rate_b / value, 3), "tile_family": info["tile"],
+            "block_steps": info["block_steps"], "workgroups": info["workgroups"]}
+        plan.close()
+        del items
+        # Differentiable: 16 x 1024^2 f32, 200 steps, forward + backward.
+        fd, md, gd = workloads.differentiable_f32(size=S)
+        Fd, Md, Gd = (torch.from_numpy(a).to(dev) for a in (fd, md, gd))
+
+        def fwd_bwd():
+            Fr = Fd.detach().requires_grad_(True)
+            Mr = Md.detach().requires_grad_(True)
+            gc.geodesic_chain(Fr, Mr, 200, op="dilate", checkpoint_every=32).backward(Gd)
+
+        def fwd_only():
+            with torch.no_grad():
+                gc.geodesic_chain(Fd, Md, 200, op="dilate", checkpoint_every=32)
+
+        px_d = Fd.numel() * 200
+        ms_fb = timed(fwd_bwd, 3, 1)
+        ms_fo = timed(fwd_only, 3, 1)
+        extra["fwd_bwd_16x1024_f32_200"] = {
+            "gpx_steps_per_s": round(px_d / ms_fb / 1e6, 2), "ms": round(ms_fb, 3),
+            "forward_only_gpx_steps_per_s": round(px_d / ms_fo / 1e6, 2),
+            "vs_plain": round(px_d / ms_fb / 1e6 / value, 4), "checkpoint_every": 32}
+        del Fd, Md, Gd
         for dt_name, dt in (("u8", np.uint8), ("f32", np.float32), ("f64", np.float64)):
             x = torch.from_numpy(workloads.plain_input(dt, size=S)).to(dev)
             y = torch.empty_like(x)
