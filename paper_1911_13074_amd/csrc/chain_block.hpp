@@ -127,6 +127,24 @@ __device__ __forceinline__ double lane_shift(double v) {
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// Two adjacent elements moved as one access (CW == 2 rows).
+template <typename T> struct Pair;
+template <> struct Pair<uint8_t> { using type = uint16_t; };
+template <> struct Pair<float> { using type = float2; };
+template <> struct Pair<double> { using type = double2; };
+
+__device__ __forceinline__ void split_pair(uint16_t p, uint32_t &a, uint32_t &b) { a = p & 0xFFu; b = p >> 8; }
+__device__ __forceinline__ void split_pair(float2 p, float &a, float &b) { a = p.x; b = p.y; }
+__device__ __forceinline__ void split_pair(double2 p, double &a, double &b) { a = p.x; b = p.y; }
+__device__ __forceinline__ uint16_t make_pair(uint32_t a, uint32_t b, uint8_t *) { return (uint16_t)(a | (b << 8)); }
+__device__ __forceinline__ float2 make_pair(float a, float b, float *) { return make_float2(a, b); }
+__device__ __forceinline__ double2 make_pair(double a, double b, double *) { return make_double2(a, b); }
+
+template <typename T>
+__device__ __forceinline__ bool pair_aligned(const T *p) {
+    return ((uintptr_t)p & (2 * sizeof(T) - 1)) == 0;
+}
+
 __device__ __forceinline__ uint32_t to_reg(uint8_t v) { return v; }
 __device__ __forceinline__ float to_reg(float v) { return v; }
 __device__ __forceinline__ double to_reg(double v) { return v; }
@@ -174,21 +192,50 @@ __device__ __forceinline__ uint32_t chain_block_body(const BlockArgs &a, int rx0
     R m[CLAMP ? RPW : 1][CLAMP ? CW : 1];
 
     // ---- load region (state and mask) ----
+    // Fast path (uniform per workgroup): the region lies inside the image and
+    // every lane's column pair is aligned, so each row is one access per lane
+    // and array with no bounds checks and no divergent branches.
+    constexpr int RX = 64 * CW;
+    constexpr int RY = NW * RPW;
+    bool fast = false;
+    if constexpr (CW == 2) {
+        fast = rx0 >= 0 && ry0 >= 0 && rx0 + RX <= a.width && ry0 + RY <= a.height && (rx0 & 1) == 0 &&
+               (a.pitch & 1) == 0 && pair_aligned(src) && (MODE != MODE_GEODESIC || pair_aligned(msk));
+    }
+    if (fast) {
+        if constexpr (CW == 2) {
+            using PT = typename Pair<T>::type;
+            const int64_t base = (int64_t)(ry0 + w * RPW) * a.pitch + rx0 + lane * 2;
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-        const int y = ry0 + w * RPW + r;
-        const bool yin = (unsigned)y < (unsigned)a.height;
-#pragma unroll
-        for (int c = 0; c < CW; ++c) {
-            const int x = rx0 + lane * CW + c;
-            const bool in = yin && (unsigned)x < (unsigned)a.width;
-            const int64_t off = (int64_t)y * a.pitch + x;
-            v[r][c] = in ? to_reg(src[off]) : B::bottom();
+            for (int r = 0; r < RPW; ++r)
+                split_pair(*reinterpret_cast<const PT *>(src + base + r * a.pitch), v[r][0], v[r][1]);
             if constexpr (CLAMP) {
-                if constexpr (MODE == MODE_GEODESIC)
-                    m[r][c] = in ? to_reg(msk[off]) : B::bottom();
-                else
-                    m[r][c] = in ? B::top() : B::bottom();
+#pragma unroll
+                for (int r = 0; r < RPW; ++r) {
+                    if constexpr (MODE == MODE_GEODESIC)
+                        split_pair(*reinterpret_cast<const PT *>(msk + base + r * a.pitch), m[r][0], m[r][1]);
+                    else
+                        m[r][0] = m[r][1] = B::top();
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const int y = ry0 + w * RPW + r;
+            const bool yin = (unsigned)y < (unsigned)a.height;
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                const int x = rx0 + lane * CW + c;
+                const bool in = yin && (unsigned)x < (unsigned)a.width;
+                const int64_t off = (int64_t)y * a.pitch + x;
+                v[r][c] = in ? to_reg(src[off]) : B::bottom();
+                if constexpr (CLAMP) {
+                    if constexpr (MODE == MODE_GEODESIC)
+                        m[r][c] = in ? to_reg(msk[off]) : B::bottom();
+                    else
+                        m[r][c] = in ? B::top() : B::bottom();
+                }
             }
         }
     }
@@ -206,7 +253,17 @@ __device__ __forceinline__ uint32_t chain_block_body(const BlockArgs &a, int rx0
     }
     uint32_t step_bits = 0;
 
-    for (int s = 0; s < k; ++s) {
+    // Rows still needed after step s: within k-1-s of the core, plus one row
+    // either side for the row pass.  That band only shrinks, so each wave is
+    // busy up to some step and idle from then on; an idle wave only takes
+    // the barriers (its stale rows are never read by a needed row again).
+    // Splitting the loop there keeps each step one branch-free block, which
+    // lets the compiler overlap the LDS exchange with the column pass.
+    const int busy_a = w * RPW + RPW - (halo - k);            // s < busy_a
+    const int busy_b = halo + a.core_y + k - w * RPW;          // s < busy_b
+    const int busy = __builtin_amdgcn_readfirstlane(max(0, min(k, min(busy_a, busy_b))));
+
+    for (int s = 0; s < busy; ++s) {
         // ---- 1. row pass ----
         R h[RPW][CW];
 #pragma unroll
@@ -273,20 +330,39 @@ __device__ __forceinline__ uint32_t chain_block_body(const BlockArgs &a, int rx0
             if (changed) step_bits |= 1u << s;
         }
     }
+    for (int s = busy; s < k; ++s) __syncthreads();
 
     // ---- store the core ----
+    // Pairs whose two columns are both core pixels inside the image go out as
+    // one access when aligned (all of them on the fast path); the rest one by
+    // one.  Stores need no waits, so the per-lane conditions cost little.
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
         const int ry = w * RPW + r;
         const int y = ry0 + ry;
         const bool yok = ry >= halo && ry < halo + a.core_y && y < a.height;
         if (!yok) continue;
-#pragma unroll
-        for (int c = 0; c < CW; ++c) {
-            const int cx = lane * CW + c;
+        if constexpr (CW == 2) {
+            const int cx = lane * 2;
             const int x = rx0 + cx;
-            if (cx >= halo && cx < halo + a.core_x && x < a.width)
-                from_reg(dst + (int64_t)y * a.pitch + x, v[r][c]);
+            T *p = dst + (int64_t)y * a.pitch + x;
+            const bool in0 = cx >= halo && cx < halo + a.core_x && x < a.width;
+            const bool in1 = cx + 1 >= halo && cx + 1 < halo + a.core_x && x + 1 < a.width;
+            if (in0 && in1 && (fast || pair_aligned(p))) {
+                using PT = typename Pair<T>::type;
+                *reinterpret_cast<PT *>(p) = make_pair(v[r][0], v[r][1], p);
+            } else {
+                if (in0) from_reg(p, v[r][0]);
+                if (in1) from_reg(p + 1, v[r][1]);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                const int cx = lane * CW + c;
+                const int x = rx0 + cx;
+                if (cx >= halo && cx < halo + a.core_x && x < a.width)
+                    from_reg(dst + (int64_t)y * a.pitch + x, v[r][c]);
+            }
         }
     }
     return step_bits;

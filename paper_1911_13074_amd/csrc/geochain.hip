@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -100,7 +101,7 @@ static std::mutex g_tune_mu;
 static int g_tune_k = 0;      // 0 = built-in
 static int g_tune_tile = -1;  // -1 = built-in
 
-enum { FAM_128 = 0, FAM_64 = 1, NUM_FAMS = 2 };
+enum { FAM_128 = 0, FAM_64 = 1, FAM_128W = 2, NUM_FAMS = 3 };
 
 template <typename T, int FAM> struct Family;
 // 128 x 128 region: 2 columns per lane; 8 waves of 16 rows (16 waves of 8
@@ -117,7 +118,15 @@ template <typename T> struct Family<T, FAM_64> {
     static constexpr int NW = 8;
 };
 
-static int region_side(int fam) { return fam == FAM_128 ? 128 : 64; }
+// 128 x 128 region with twice the waves: 16 waves of 8 rows (f64: 16 waves
+// of 8 rows as well, i.e. the same as FAM_128).
+template <typename T> struct Family<T, FAM_128W> {
+    static constexpr int CW = 2;
+    static constexpr int RPW = 8;
+    static constexpr int NW = 16;
+};
+
+static int region_side(int fam) { return fam == FAM_64 ? 64 : 128; }
 
 struct Plan1 {
     int fam;
@@ -128,8 +137,8 @@ struct Plan1 {
 static Plan1 choose_plan(const gc_shape &s, int64_t n, bool detect) {
     Plan1 p;
     const int64_t side = std::max(s.width, s.height);
-    p.fam = side >= 384 ? FAM_128 : FAM_64;
-    p.k = p.fam == FAM_128 ? 32 : 16;
+    p.fam = side >= 384 ? FAM_128W : FAM_64;
+    p.k = p.fam == FAM_64 ? 16 : 32;
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
         if (g_tune_tile >= 0 && g_tune_tile < NUM_FAMS) p.fam = g_tune_tile;
@@ -264,8 +273,9 @@ static void launch_block(const BlockArgs &a, int grid, hipStream_t st) {
 
 template <typename T, int OP, int MODE, bool DETECT>
 static LaunchFn pick_fam(int fam) {
-    return fam == FAM_128 ? &launch_block<T, OP, MODE, DETECT, FAM_128>
-                          : &launch_block<T, OP, MODE, DETECT, FAM_64>;
+    if (fam == FAM_64) return &launch_block<T, OP, MODE, DETECT, FAM_64>;
+    if (fam == FAM_128W) return &launch_block<T, OP, MODE, DETECT, FAM_128W>;
+    return &launch_block<T, OP, MODE, DETECT, FAM_128>;
 }
 
 template <typename T>
@@ -524,7 +534,9 @@ static PersistentFns persistent_fns_t() {
 
 template <typename T, int OP, int MODE>
 static PersistentFns persistent_fns_m(int fam) {
-    return fam == FAM_128 ? persistent_fns_t<T, OP, MODE, FAM_128>() : persistent_fns_t<T, OP, MODE, FAM_64>();
+    if (fam == FAM_64) return persistent_fns_t<T, OP, MODE, FAM_64>();
+    if (fam == FAM_128W) return persistent_fns_t<T, OP, MODE, FAM_128W>();
+    return persistent_fns_t<T, OP, MODE, FAM_128>();
 }
 
 template <typename T>
@@ -548,7 +560,9 @@ static PersistentFns persistent_fns(gc_dtype d, int op, int mode, int fam) {
 // Largest steps per block the persistent kernel accepts: the halo must not
 // reach past the neighbouring tiles (k <= core = side - 2k).
 static int persistent_kmax(int fam) { return region_side(fam) / 3; }
-static int default_persistent_k(int fam) { return fam == FAM_128 ? 32 : 16; }
+// Built-in steps per block for batches: with many items in flight the
+// per-item latency is hidden, so a shallower block (less halo) wins.
+static int default_persistent_k(int fam) { return fam == FAM_64 ? 12 : 20; }
 
 // ---- autotuner table ----
 struct TuneKey {
@@ -559,8 +573,8 @@ struct TuneKey {
 };
 struct TuneVal {
     int best_fam = FAM_128;
-    int k[NUM_FAMS] = {0, 0};
-    double rate[NUM_FAMS] = {0, 0};  // pixel-steps per second
+    int k[NUM_FAMS] = {};
+    double rate[NUM_FAMS] = {};  // pixel-steps per second
 };
 static std::mutex g_autotune_mu;
 static std::map<TuneKey, TuneVal> g_autotune;
@@ -616,6 +630,7 @@ static void plan_free(gc_plan *p) {
 struct PlanChoice {
     int fam;
     std::vector<int> k;  // per item
+    int wgs_per_cu = 0;  // 0: as many as fit
 };
 
 // Tile family for the whole plan and steps per block for each item: from
@@ -656,6 +671,7 @@ static PlanChoice choose_plan_batch(gc_dtype d, int op, int mode, const std::vec
         }
     }
     if (forced_fam >= 0) c.fam = forced_fam;
+    if (const char *e = getenv("GC_PLAN_WGS_PER_CU")) c.wgs_per_cu = atoi(e);
     for (size_t i = 0; i < items.size(); ++i) {
         int k = default_persistent_k(c.fam);
         if (all_tuned && vals[i].k[c.fam] > 0) k = vals[i].k[c.fam];
@@ -797,6 +813,7 @@ static int plan_build(gc_dtype dtype, int op, const gc_item *items, int32_t n_it
         return bail(fail(GC_ERR_HIP, "occupancy query failed"));
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess)
         return bail(fail(GC_ERR_HIP, "CU count query failed"));
+    if (choice.wgs_per_cu > 0) per_cu = std::min(per_cu, choice.wgs_per_cu);
     p->grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>((int64_t)std::max(per_cu, 1) * cus,
                                                                std::max<int32_t>(p->n_items, 1)));
 
@@ -827,7 +844,6 @@ static int plan_build(gc_dtype dtype, int op, const gc_item *items, int32_t n_it
         a.images = p->images_d;
         a.items = p->items_d;
         a.n_items = p->n_items;
-        a.counter = p->words_d;
         a.error = p->words_d + 1;
         a.flags = p->words_d + 2;
         a.spin_limit = 1u << 18;

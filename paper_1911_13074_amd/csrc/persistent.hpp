@@ -5,18 +5,18 @@
 // core from step b*k to step min((b+1)*k, n) with the same register-resident
 // body as the per-launch kernel (chain_block.hpp).  Items sit in one global
 // list ordered by block index, so the list is a valid topological order of
-// the dependencies below.  Workgroups take items in list order from an atomic
-// counter and, before loading, wait until the item's 3x3 neighbourhood of
+// the dependencies below.  Workgroup g takes items g, g+G, g+2G, ... in list
+// order and, before loading, waits until the item's 3x3 neighbourhood of
 // tiles has finished block b-1 (a per-tile counter, released after the
 // tile's stores).  This is the GPU counterpart of the paper's per-filter row
 // counters with acquire/release semantics (Section 3.5): here the counters
 // are per tile and per block of k steps instead of per row and per step.
 //
-// Progress: an item only waits for items earlier in the list, and every
-// earlier item was taken by a workgroup that is already running, so the
-// earliest unfinished item can always proceed; no co-residency of the whole
-// grid is assumed.  Every wait is bounded: past spin_limit polls the item
-// sets the error word and goes on, so the launch always drains.
+// Progress: an item only waits for items earlier in the list, so the
+// earliest unfinished item can always proceed once its workgroup runs; the
+// grid is sized to what fits on the device at once.  Every wait is bounded:
+// past spin_limit polls the item sets the error word and goes on, so the
+// launch always drains.
 //
 // Buffers: block b reads state from marker (b = 0) or ws[(b-1)&1] and writes
 // ws[b&1], except the last block which writes out.  A tile's block b may
@@ -58,7 +58,6 @@ struct PersistentArgs {
     const PlanImage *images;
     const PlanItem *items;
     int32_t n_items;
-    uint32_t *counter;   // next item to take
     uint32_t *flags;     // per tile: number of blocks finished
     uint32_t *error;     // bit 0: a wait hit spin_limit
     uint32_t spin_limit;
@@ -90,16 +89,13 @@ template <typename T, int OP, int MODE, int CW, int RPW, int NW>
 __global__ __launch_bounds__(64 * NW) void persistent_chain_kernel(PersistentArgs a) {
     using R = typename RegOf<T>::type;
     __shared__ R xch[2][NW][2][64 * CW];
-    __shared__ int s_item;
 
     const int tid = threadIdx.x;
-    // Control flow below stays uniform across the workgroup: the loop
-    // condition comes from LDS through readfirstlane, and the one-lane
-    // sections are closed by a barrier before anything reads their result.
-    if (tid == 0) s_item = (int)atomicAdd(a.counter, 1u);
-    __syncthreads();
-    int it = __builtin_amdgcn_readfirstlane(s_item);
-    while (it < a.n_items) {
+    // Items are dealt round-robin: workgroup g takes g, g + G, g + 2G, ...
+    // in list order, so no shared counter is needed.  Progress: the earliest
+    // unfinished item's dependencies are all finished, and its workgroup has
+    // finished every earlier item of its own, so it is working on it.
+    for (int it = blockIdx.x; it < a.n_items; it += gridDim.x) {
         const PlanItem item = a.items[it];
         const PlanImage &im = a.images[item.image];
         const int tx = item.tile % im.tiles_x;
@@ -114,9 +110,14 @@ __global__ __launch_bounds__(64 * NW) void persistent_chain_kernel(PersistentArg
             const bool ok = wait_neighbours(a, im, tx, ty, (uint32_t)b);
             if (!ok && tid == 0) atomicOr(a.error, 1u);
         }
+        // Make the neighbours' stores visible to this workgroup's loads: the
+        // waiting wave acquires at agent scope (this invalidates the CU's L1
+        // and the stale lines of the XCD's L2, shared by every wave of the
+        // workgroup) and the barrier orders the other waves after it.  One
+        // acquire per workgroup instead of one per wave: each is an L2
+        // invalidate.
+        if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         __syncthreads();
-        // Make the neighbours' stores visible to this workgroup's loads.
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 
         // ---- the block itself ----
         const int k_b = (b == im.blocks - 1) ? im.n_steps - b * im.k : im.k;
@@ -137,17 +138,14 @@ __global__ __launch_bounds__(64 * NW) void persistent_chain_kernel(PersistentArg
         const int ry0 = ty * im.core_y - im.k;
         chain_block_dispatch<T, OP, MODE, false, CW, RPW, NW>(ba, rx0, ry0, xch);
 
-        // ---- publish: stores first, then the tile's counter; take the next item ----
+        // ---- publish: stores first, then the tile's counter ----
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
         if (tid == 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __hip_atomic_store(a.flags + im.flag_base + item.tile, (uint32_t)(b + 1), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-            s_item = (int)atomicAdd(a.counter, 1u);
         }
-        __syncthreads();
-        it = __builtin_amdgcn_readfirstlane(s_item);
     }
 }
 

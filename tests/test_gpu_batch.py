@@ -68,7 +68,7 @@ def test_uneven_batch(dtype, op):
     check_items(op, items, plan.outs)
 
 
-@pytest.mark.parametrize("tile,k", [(0, 8), (0, 21), (0, 42), (1, 5), (1, 21)])
+@pytest.mark.parametrize("tile,k", [(0, 8), (0, 21), (0, 42), (1, 5), (1, 21), (2, 32)])
 def test_launch_shapes(tile, k):
     gc.set_tuning(k, tile)
     items = make_batch(np.uint8, seed=tile * 100 + k, count=6, lo=50, hi=400, n_lo=k, n_hi=3 * k + 7)
