@@ -368,13 +368,201 @@ __device__ __forceinline__ uint32_t chain_block_body(const BlockArgs &a, int rx0
     return step_bits;
 }
 
+// Two-group layout: a wave covers RX = 32*CW columns and 2*RPW rows.
+// Lanes 0..31 (group 0) hold the wave's first RPW rows, lanes 32..63 (group
+// 1) the next RPW rows; lane l holds columns [(l%32)*CW, (l%32+1)*CW).  The
+// DPP wave shifts of the row pass cross from lane 31 to lane 32 only at the
+// region's left/right edge, where wrong values are tolerated.  Every group
+// publishes its first and last row-pass rows in LDS and reads the row above
+// and below it from there (per-lane addresses, no selects).  A narrower
+// region (96 columns for CW = 3) lets a 64 x 64 core run with a 16-pixel
+// halo instead of 32.
+template <typename T, int OP, int MODE, bool CLAMP, bool DETECT, int CW, int RPW, int NW>
+__device__ __forceinline__ uint32_t chain_block_body_g2(const BlockArgs &a, int rx0, int ry0,
+                                                        typename RegOf<T>::type (*xch)[NW][4][32 * CW]) {
+    using R = typename RegOf<T>::type;
+    using B = Bounds<R, OP>;
+    using P = Pick<OP>;
+    constexpr int RX = 32 * CW;
+    constexpr int WR = 2 * RPW;  // rows per wave
+    constexpr int RY = NW * WR;
+
+    const int lane = threadIdx.x & 63;
+    const int grp = lane >> 5;
+    const int lc = lane & 31;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int row0 = w * WR + grp * RPW;  // first region row of this lane
+    const T *src = static_cast<const T *>(a.src);
+    const T *msk = static_cast<const T *>(a.mask);
+    T *dst = static_cast<T *>(a.dst);
+    const int k = a.k;
+    const int halo = a.halo;
+
+    R v[RPW][CW];
+    R m[CLAMP ? RPW : 1][CLAMP ? CW : 1];
+
+    // ---- load region ----
+    const bool inside = rx0 >= 0 && ry0 >= 0 && rx0 + RX <= a.width && ry0 + RY <= a.height;
+    if (inside) {
+        const int64_t base = (int64_t)(ry0 + row0) * a.pitch + rx0 + lc * CW;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                v[r][c] = to_reg(src[base + r * a.pitch + c]);
+                if constexpr (CLAMP) {
+                    if constexpr (MODE == MODE_GEODESIC)
+                        m[r][c] = to_reg(msk[base + r * a.pitch + c]);
+                    else
+                        m[r][c] = B::top();
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const int y = ry0 + row0 + r;
+            const bool yin = (unsigned)y < (unsigned)a.height;
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                const int x = rx0 + lc * CW + c;
+                const bool in = yin && (unsigned)x < (unsigned)a.width;
+                const int64_t off = (int64_t)y * a.pitch + x;
+                v[r][c] = in ? to_reg(src[off]) : B::bottom();
+                if constexpr (CLAMP) {
+                    if constexpr (MODE == MODE_GEODESIC)
+                        m[r][c] = in ? to_reg(msk[off]) : B::bottom();
+                    else
+                        m[r][c] = in ? B::top() : B::bottom();
+                }
+            }
+        }
+    }
+
+    // Core ownership for change detection (per lane: rows depend on group).
+    uint64_t col_in_core[CW];
+    if constexpr (DETECT) {
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+            const int cx = lc * CW + c;
+            col_in_core[c] = __builtin_amdgcn_ballot_w64(cx >= halo && cx < halo + a.core_x &&
+                                                         rx0 + cx < a.width);
+        }
+    }
+    uint32_t step_bits = 0;
+
+    // Idle from the step on which the wave's rows leave the needed band (see
+    // chain_block_body).
+    const int busy_a = w * WR + WR - (halo - k);
+    const int busy_b = halo + a.core_y + k - w * WR;
+    const int busy = __builtin_amdgcn_readfirstlane(max(0, min(k, min(busy_a, busy_b))));
+    // LDS slots per wave: [group * 2 + 0] first row, [group * 2 + 1] last
+    // row.  The row above a group's first row is the last row of the group
+    // before it (group 1 of the wave above for group 0); the row below its
+    // last row is the first row of the group after it (wrapping at the
+    // region's edge: harmless there).
+    const int wa = w > 0 ? w - 1 : NW - 1;
+    const int wb = w < NW - 1 ? w + 1 : 0;
+    const int above_w = grp ? w : wa, above_slot = grp ? 1 : 3;
+    const int below_w = grp ? wb : w, below_slot = grp ? 0 : 2;
+
+    for (int s = 0; s < busy; ++s) {
+        // ---- 1. row pass ----
+        R h[RPW][CW];
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const R left = lane_shift<DPP_WAVE_SHR1>(v[r][CW - 1]);
+            const R right = lane_shift<DPP_WAVE_SHL1>(v[r][0]);
+            if constexpr (CW == 3) {
+                // Both partial extrema feed two outputs each, so the
+                // compiler keeps them and folds the neighbour lanes into
+                // DPP-sourced max/min: 5 operations for 3 pixels.
+                const R t1 = P::pick(v[r][0], v[r][1]);
+                const R t2 = P::pick(v[r][1], v[r][2]);
+                h[r][0] = P::pick(t1, left);
+                h[r][1] = P::pick(t1, t2);
+                h[r][2] = P::pick(t2, right);
+            } else {
+#pragma unroll
+                for (int c = 0; c < CW; ++c) {
+                    const R l = c == 0 ? left : v[r][c - 1];
+                    const R rr = c == CW - 1 ? right : v[r][c + 1];
+                    h[r][c] = P::pick(P::pick(v[r][c], rr), l);
+                }
+            }
+        }
+        // ---- 2. exchange through LDS ----
+        const int par = s & 1;
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+            xch[par][w][grp * 2][lc * CW + c] = h[0][c];
+            xch[par][w][grp * 2 + 1][lc * CW + c] = h[RPW - 1][c];
+        }
+        __syncthreads();
+        R above[CW], below[CW];
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+            above[c] = xch[par][above_w][above_slot][lc * CW + c];
+            below[c] = xch[par][below_w][below_slot][lc * CW + c];
+        }
+        // ---- 3. column pass + clamp ----
+        uint64_t changed = 0;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const int ry = row0 + r;
+            const bool row_in_core = DETECT && ry >= halo && ry < halo + a.core_y && ry0 + ry < a.height;
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                const R up = r == 0 ? above[c] : h[r - 1][c];
+                const R dn = r == RPW - 1 ? below[c] : h[r + 1][c];
+                R nv = P::pick(P::pick(up, h[r][c]), dn);
+                if constexpr (CLAMP) nv = P::clamp(nv, m[r][c]);
+                if constexpr (DETECT)
+                    changed |= __builtin_amdgcn_ballot_w64(row_in_core && nv != v[r][c]) & col_in_core[c];
+                v[r][c] = nv;
+            }
+        }
+        if constexpr (DETECT) {
+            if (changed) step_bits |= 1u << s;
+        }
+    }
+    for (int s = busy; s < k; ++s) __syncthreads();
+
+    // ---- store the core ----
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        const int ry = row0 + r;
+        const int y = ry0 + ry;
+        if (!(ry >= halo && ry < halo + a.core_y && y < a.height)) continue;
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+            const int cx = lc * CW + c;
+            const int x = rx0 + cx;
+            if (cx >= halo && cx < halo + a.core_x && x < a.width)
+                from_reg(dst + (int64_t)y * a.pitch + x, v[r][c]);
+        }
+    }
+    return step_bits;
+}
+
+// Lanes per column group: 64 (one group) or 32 (two groups).
+template <int G> constexpr int lanes_per_group() { return 64 / G; }
+
 // Plain chains skip the border fence for regions entirely inside the image.
-template <typename T, int OP, int MODE, bool DETECT, int CW, int RPW, int NW>
-__device__ __forceinline__ uint32_t chain_block_dispatch(const BlockArgs &a, int rx0, int ry0,
-                                                         typename RegOf<T>::type (*xch)[NW][2][64 * CW]) {
-    constexpr int RX = 64 * CW;
-    constexpr int RY = NW * RPW;
-    if constexpr (MODE == MODE_PLAIN) {
+template <typename T, int OP, int MODE, bool DETECT, int CW, int RPW, int NW, int G = 1>
+__device__ __forceinline__ uint32_t chain_block_dispatch(
+    const BlockArgs &a, int rx0, int ry0, typename RegOf<T>::type (*xch)[NW][2 * G][lanes_per_group<G>() * CW]) {
+    constexpr int RX = lanes_per_group<G>() * CW;
+    constexpr int RY = NW * RPW * G;
+    if constexpr (G == 2) {
+        if constexpr (MODE == MODE_PLAIN) {
+            const bool inside = rx0 >= 0 && ry0 >= 0 && rx0 + RX <= a.width && ry0 + RY <= a.height;
+            if (inside) return chain_block_body_g2<T, OP, MODE, false, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
+            return chain_block_body_g2<T, OP, MODE, true, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
+        } else {
+            return chain_block_body_g2<T, OP, MODE, true, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
+        }
+    } else if constexpr (MODE == MODE_PLAIN) {
         const bool inside = rx0 >= 0 && ry0 >= 0 && rx0 + RX <= a.width && ry0 + RY <= a.height;
         if (inside) return chain_block_body<T, OP, MODE, false, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
         return chain_block_body<T, OP, MODE, true, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
@@ -383,7 +571,7 @@ __device__ __forceinline__ uint32_t chain_block_dispatch(const BlockArgs &a, int
     }
 }
 
-template <typename T, int OP, int MODE, bool DETECT, int CW, int RPW, int NW>
+template <typename T, int OP, int MODE, bool DETECT, int CW, int RPW, int NW, int G = 1>
 __global__ __launch_bounds__(64 * NW) void chain_block_kernel(BlockArgs a) {
     if (DETECT && a.prev_word != nullptr) {
         // The image stopped changing in an earlier launch: nothing to do.
@@ -395,8 +583,8 @@ __global__ __launch_bounds__(64 * NW) void chain_block_kernel(BlockArgs a) {
     const int rx0 = tx * a.core_x - a.halo;
     const int ry0 = ty * a.core_y - a.halo;
     using R = typename RegOf<T>::type;
-    __shared__ R xch[2][NW][2][64 * CW];
-    const uint32_t bits = chain_block_dispatch<T, OP, MODE, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
+    __shared__ R xch[2][NW][2 * G][lanes_per_group<G>() * CW];
+    const uint32_t bits = chain_block_dispatch<T, OP, MODE, DETECT, CW, RPW, NW, G>(a, rx0, ry0, xch);
     if constexpr (DETECT) {
         if (bits != 0 && (threadIdx.x & 63) == 0) atomicOr(a.change_word, bits);
     }

@@ -101,21 +101,25 @@ static std::mutex g_tune_mu;
 static int g_tune_k = 0;      // 0 = built-in
 static int g_tune_tile = -1;  // -1 = built-in
 
-enum { FAM_128 = 0, FAM_64 = 1, FAM_128W = 2, NUM_FAMS = 3 };
+enum { FAM_128 = 0, FAM_64 = 1, FAM_128W = 2, FAM_96 = 3, FAM_96W = 4, NUM_FAMS = 5 };
 
 template <typename T, int FAM> struct Family;
+// G: column groups per wave (1: 64 lanes across; 2: two 32-lane groups
+// stacked vertically, see chain_block_body_g2).
 // 128 x 128 region: 2 columns per lane; 8 waves of 16 rows (16 waves of 8
 // rows for f64, whose registers are twice as wide).
 template <typename T> struct Family<T, FAM_128> {
     static constexpr int CW = 2;
     static constexpr int RPW = sizeof(T) == 8 ? 8 : 16;
     static constexpr int NW = sizeof(T) == 8 ? 16 : 8;
+    static constexpr int G = 1;
 };
 // 64 x 64 region for small images: 1 column per lane, 8 waves of 8 rows.
 template <typename T> struct Family<T, FAM_64> {
     static constexpr int CW = 1;
     static constexpr int RPW = 8;
     static constexpr int NW = 8;
+    static constexpr int G = 1;
 };
 
 // 128 x 128 region with twice the waves: 16 waves of 8 rows (f64: 16 waves
@@ -124,9 +128,31 @@ template <typename T> struct Family<T, FAM_128W> {
     static constexpr int CW = 2;
     static constexpr int RPW = 8;
     static constexpr int NW = 16;
+    static constexpr int G = 1;
+};
+// 96 x 96 region, two 32-lane groups of 3 columns: 8 waves of 2 x 6 rows.
+template <typename T> struct Family<T, FAM_96> {
+    static constexpr int CW = 3;
+    static constexpr int RPW = 6;
+    static constexpr int NW = 8;
+    static constexpr int G = 2;
+};
+// 96 x 96 region with 16 waves of 2 x 3 rows.
+template <typename T> struct Family<T, FAM_96W> {
+    static constexpr int CW = 3;
+    static constexpr int RPW = 3;
+    static constexpr int NW = 16;
+    static constexpr int G = 2;
 };
 
-static int region_side(int fam) { return fam == FAM_64 ? 64 : 128; }
+static int region_side(int fam) {
+    switch (fam) {
+        case FAM_64: return 64;
+        case FAM_96:
+        case FAM_96W: return 96;
+        default: return 128;
+    }
+}
 
 struct Plan1 {
     int fam;
@@ -138,7 +164,7 @@ static Plan1 choose_plan(const gc_shape &s, int64_t n, bool detect) {
     Plan1 p;
     const int64_t side = std::max(s.width, s.height);
     p.fam = side >= 384 ? FAM_128W : FAM_64;
-    p.k = p.fam == FAM_64 ? 16 : 32;
+    p.k = region_side(p.fam) == 128 ? 32 : 16;
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
         if (g_tune_tile >= 0 && g_tune_tile < NUM_FAMS) p.fam = g_tune_tile;
@@ -267,15 +293,19 @@ using LaunchFn = void (*)(const BlockArgs &, int grid, hipStream_t);
 template <typename T, int OP, int MODE, bool DETECT, int FAM>
 static void launch_block(const BlockArgs &a, int grid, hipStream_t st) {
     using F = Family<T, FAM>;
-    hipLaunchKernelGGL((chain_block_kernel<T, OP, MODE, DETECT, F::CW, F::RPW, F::NW>),
+    hipLaunchKernelGGL((chain_block_kernel<T, OP, MODE, DETECT, F::CW, F::RPW, F::NW, F::G>),
                        dim3(grid), dim3(64 * F::NW), 0, st, a);
 }
 
 template <typename T, int OP, int MODE, bool DETECT>
 static LaunchFn pick_fam(int fam) {
-    if (fam == FAM_64) return &launch_block<T, OP, MODE, DETECT, FAM_64>;
-    if (fam == FAM_128W) return &launch_block<T, OP, MODE, DETECT, FAM_128W>;
-    return &launch_block<T, OP, MODE, DETECT, FAM_128>;
+    switch (fam) {
+        case FAM_64: return &launch_block<T, OP, MODE, DETECT, FAM_64>;
+        case FAM_128W: return &launch_block<T, OP, MODE, DETECT, FAM_128W>;
+        case FAM_96: return &launch_block<T, OP, MODE, DETECT, FAM_96>;
+        case FAM_96W: return &launch_block<T, OP, MODE, DETECT, FAM_96W>;
+        default: return &launch_block<T, OP, MODE, DETECT, FAM_128>;
+    }
 }
 
 template <typename T>
@@ -518,7 +548,7 @@ struct PersistentFns {
 template <typename T, int OP, int MODE, int FAM>
 static void launch_persistent(const PersistentArgs &a, int grid, hipStream_t st) {
     using F = Family<T, FAM>;
-    hipLaunchKernelGGL((persistent_chain_kernel<T, OP, MODE, F::CW, F::RPW, F::NW>), dim3(grid),
+    hipLaunchKernelGGL((persistent_chain_kernel<T, OP, MODE, F::CW, F::RPW, F::NW, F::G>), dim3(grid),
                        dim3(64 * F::NW), 0, st, a);
 }
 
@@ -526,7 +556,7 @@ template <typename T, int OP, int MODE, int FAM>
 static PersistentFns persistent_fns_t() {
     using F = Family<T, FAM>;
     PersistentFns f;
-    f.kernel = (const void *)&persistent_chain_kernel<T, OP, MODE, F::CW, F::RPW, F::NW>;
+    f.kernel = (const void *)&persistent_chain_kernel<T, OP, MODE, F::CW, F::RPW, F::NW, F::G>;
     f.launch = &launch_persistent<T, OP, MODE, FAM>;
     f.threads = 64 * F::NW;
     return f;
@@ -534,9 +564,13 @@ static PersistentFns persistent_fns_t() {
 
 template <typename T, int OP, int MODE>
 static PersistentFns persistent_fns_m(int fam) {
-    if (fam == FAM_64) return persistent_fns_t<T, OP, MODE, FAM_64>();
-    if (fam == FAM_128W) return persistent_fns_t<T, OP, MODE, FAM_128W>();
-    return persistent_fns_t<T, OP, MODE, FAM_128>();
+    switch (fam) {
+        case FAM_64: return persistent_fns_t<T, OP, MODE, FAM_64>();
+        case FAM_128W: return persistent_fns_t<T, OP, MODE, FAM_128W>();
+        case FAM_96: return persistent_fns_t<T, OP, MODE, FAM_96>();
+        case FAM_96W: return persistent_fns_t<T, OP, MODE, FAM_96W>();
+        default: return persistent_fns_t<T, OP, MODE, FAM_128>();
+    }
 }
 
 template <typename T>
@@ -562,7 +596,10 @@ static PersistentFns persistent_fns(gc_dtype d, int op, int mode, int fam) {
 static int persistent_kmax(int fam) { return region_side(fam) / 3; }
 // Built-in steps per block for batches: with many items in flight the
 // per-item latency is hidden, so a shallower block (less halo) wins.
-static int default_persistent_k(int fam) { return fam == FAM_64 ? 12 : 20; }
+static int default_persistent_k(int fam) {
+    const int side = region_side(fam);
+    return side == 128 ? 20 : side == 96 ? 16 : 12;
+}
 
 // ---- autotuner table ----
 struct TuneKey {

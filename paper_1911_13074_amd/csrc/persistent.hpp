@@ -85,10 +85,10 @@ __device__ __forceinline__ bool wait_neighbours(const PersistentArgs &a, const P
     return done;
 }
 
-template <typename T, int OP, int MODE, int CW, int RPW, int NW>
+template <typename T, int OP, int MODE, int CW, int RPW, int NW, int G = 1>
 __global__ __launch_bounds__(64 * NW) void persistent_chain_kernel(PersistentArgs a) {
     using R = typename RegOf<T>::type;
-    __shared__ R xch[2][NW][2][64 * CW];
+    __shared__ R xch[2][NW][2 * G][lanes_per_group<G>() * CW];
 
     const int tid = threadIdx.x;
     // Items are dealt round-robin: workgroup g takes g, g + G, g + 2G, ...
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(64 * NW) void persistent_chain_kernel(PersistentArg
         ba.tiles_x = im.tiles_x;
         const int rx0 = tx * im.core_x - im.k;
         const int ry0 = ty * im.core_y - im.k;
-        chain_block_dispatch<T, OP, MODE, false, CW, RPW, NW>(ba, rx0, ry0, xch);
+        chain_block_dispatch<T, OP, MODE, false, CW, RPW, NW, G>(ba, rx0, ry0, xch);
 
         // ---- publish: stores first, then the tile's counter ----
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");

@@ -155,7 +155,7 @@ def test_zero_steps_and_empty():
     assert steps == 0 and conv
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("k", [1, 3, 16, 24, 32, 47])
 def test_launch_shape_sweep(tile, k):
     if tile == 1 and k > 24:
