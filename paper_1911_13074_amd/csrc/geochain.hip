@@ -20,7 +20,7 @@
 #include "geochain.h"
 #include "chain_block.hpp"
 #include "persistent.hpp"
-#include "grad_step.hpp"
+#include "grad_block.hpp"
 
 namespace geochain {
 
@@ -442,7 +442,10 @@ static int run_reconstruct(gc_dtype dtype, int op, const void *marker, const voi
     int64_t blocks = 0;      // launches issued so far (sets the ping-pong parity)
     const void *cur = marker;
     const void *result = marker;
-    int group = 4;
+    // Launches per host check: start with 8 blocks (a few hundred steps, the
+    // typical reconstruction length), then double; launches past the
+    // convergence point exit at once.
+    int group = 8;
     bool converged = false;
 
     auto make_args = [&](const void *src, void *dst, int kk, uint32_t *word, const uint32_t *prev,
@@ -988,19 +991,28 @@ static std::pair<uintptr_t, uintptr_t> batch_extent(const void *p, const gc_shap
     return {lo, lo + ((uint64_t)(n - 1) * stride + span) * es};
 }
 
-static dim3 step_grid(const gc_shape &s, int32_t n_images) {
-    return dim3((unsigned)((s.width + GT_X - 1) / GT_X), (unsigned)((s.height + GT_Y - 1) / GT_Y),
-                (unsigned)n_images);
+template <typename T>
+static dim3 block_grid(const gc_shape &s, int32_t n_images) {
+    constexpr int CY = GradTile<T>::CY;
+    return dim3((unsigned)((s.width + GB_CX - 1) / GB_CX), (unsigned)((s.height + CY - 1) / CY), (unsigned)n_images);
 }
 
 template <typename T>
-static void launch_codes(int op, const StepArgs &a, dim3 grid, hipStream_t st) {
+static void launch_codes(int op, const GradBlockArgs &a, const gc_shape &s, int32_t n, hipStream_t st) {
+    const dim3 grid = block_grid<T>(s, n), block(GradTile<T>::THREADS);
     if (op == OP_DILATE)
-        hipLaunchKernelGGL((step_codes_kernel<T, OP_DILATE>), grid, dim3(GT_THREADS), 0, st, a);
+        hipLaunchKernelGGL((block_codes_kernel<T, OP_DILATE>), grid, block, 0, st, a);
     else
-        hipLaunchKernelGGL((step_codes_kernel<T, OP_ERODE>), grid, dim3(GT_THREADS), 0, st, a);
+        hipLaunchKernelGGL((block_codes_kernel<T, OP_ERODE>), grid, block, 0, st, a);
 }
 
+template <typename T>
+static void launch_bwd(const GradBlockArgs &a, const gc_shape &s, int32_t n, hipStream_t st) {
+    hipLaunchKernelGGL((block_bwd_kernel<T>), block_grid<T>(s, n), dim3(GradTile<T>::THREADS), 0, st, a);
+}
+
+// Forward with codes: blocks of up to GB_K steps per launch, ping-pong
+// through the workspace, the last block writing out.
 static int run_fwd_codes(gc_dtype dtype, int op, const void *marker, const void *mask, void *out, uint8_t *codes,
                          const gc_shape &s, int32_t n, int64_t stride, int64_t n_steps, hipStream_t st) {
     const size_t es = elem_size(dtype);
@@ -1018,28 +1030,32 @@ static int run_fwd_codes(gc_dtype dtype, int op, const void *marker, const void 
     int rc = get_workspace(st, 2 * half, 0, &ws);
     if (rc != GC_OK) return rc;
     void *w[2] = {ws->buf, (char *)ws->buf + half};
+    const int64_t blocks = (n_steps + GB_K - 1) / GB_K;
     const void *cur = marker;
-    if (out == marker && n_steps == 1) {
+    if (out == marker && blocks == 1) {
         GC_HIP(hipMemcpyAsync(w[1], marker, batch_bytes, hipMemcpyDeviceToDevice, st));
         cur = w[1];
     }
     const int64_t codes_step = s.height * s.width;
-    const dim3 grid = step_grid(s, n);
-    for (int64_t t = 0; t < n_steps; ++t) {
-        void *dst = t == n_steps - 1 ? out : w[t & 1];
-        StepArgs a{};
+    for (int64_t b = 0; b < blocks; ++b) {
+        const int64_t t0 = b * GB_K;
+        const int kb = (int)std::min<int64_t>(GB_K, n_steps - t0);
+        void *dst = b == blocks - 1 ? out : w[b & 1];
+        GradBlockArgs a{};
         a.src = cur;
         a.mask = mask;
         a.dst = dst;
-        a.codes = codes + t * codes_step;
-        a.codes_image_stride = n_steps * codes_step;
+        a.codes = codes + t0 * codes_step;
+        a.codes_step = codes_step;
+        a.codes_image = n_steps * codes_step;
         a.image_stride = istride;
         a.pitch = s.pitch;
         a.width = (int32_t)s.width;
         a.height = (int32_t)s.height;
-        const int pr = prof_begin(st, 1);
-        if (dtype == GC_F32) launch_codes<float>(op, a, grid, st);
-        else launch_codes<double>(op, a, grid, st);
+        a.k = kb;
+        const int pr = prof_begin(st, kb);
+        if (dtype == GC_F32) launch_codes<float>(op, a, s, n, st);
+        else launch_codes<double>(op, a, s, n, st);
         prof_end(pr, st);
         GC_HIP(hipGetLastError());
         cur = dst;
@@ -1047,6 +1063,7 @@ static int run_fwd_codes(gc_dtype dtype, int op, const void *marker, const void 
     return GC_OK;
 }
 
+// Reverse pass: the same blocks from last to first.
 static int run_bwd(gc_dtype dtype, const uint8_t *codes, const void *g_out, void *g_marker, void *g_mask,
                    const gc_shape &s, int32_t n, int64_t stride, int64_t n_steps, hipStream_t st) {
     const size_t es = elem_size(dtype);
@@ -1064,25 +1081,27 @@ static int run_bwd(gc_dtype dtype, const uint8_t *codes, const void *g_out, void
     if (rc != GC_OK) return rc;
     void *w[2] = {ws->buf, (char *)ws->buf + half};
     const int64_t codes_step = s.height * s.width;
-    const dim3 grid = step_grid(s, n);
+    const int64_t blocks = (n_steps + GB_K - 1) / GB_K;
     const void *cur = g_out;
-    for (int64_t t = n_steps - 1; t >= 0; --t) {
-        void *dst = t == 0 ? g_marker : w[t & 1];
-        BwdArgs a{};
-        a.codes = codes + t * codes_step;
-        a.codes_image_stride = n_steps * codes_step;
-        a.g_in = cur;
-        a.g_out = dst;
+    for (int64_t b = blocks - 1; b >= 0; --b) {
+        const int64_t t0 = b * GB_K;
+        const int kb = (int)std::min<int64_t>(GB_K, n_steps - t0);
+        void *dst = b == 0 ? g_marker : w[b & 1];
+        GradBlockArgs a{};
+        a.src = cur;
+        a.dst = dst;
         a.g_mask = g_mask;
+        a.codes = const_cast<uint8_t *>(codes) + t0 * codes_step;
+        a.codes_step = codes_step;
+        a.codes_image = n_steps * codes_step;
         a.image_stride = istride;
         a.pitch = s.pitch;
         a.width = (int32_t)s.width;
         a.height = (int32_t)s.height;
-        const int pr = prof_begin(st, 1);
-        if (dtype == GC_F32)
-            hipLaunchKernelGGL((step_bwd_kernel<float>), grid, dim3(GT_THREADS), 0, st, a);
-        else
-            hipLaunchKernelGGL((step_bwd_kernel<double>), grid, dim3(GT_THREADS), 0, st, a);
+        a.k = kb;
+        const int pr = prof_begin(st, kb);
+        if (dtype == GC_F32) launch_bwd<float>(a, s, n, st);
+        else launch_bwd<double>(a, s, n, st);
         prof_end(pr, st);
         GC_HIP(hipGetLastError());
         cur = dst;

@@ -1,0 +1,299 @@
+// grad_block.hpp -- kernels for differentiating a geodesic chain (not part
+// of the paper, which has no backward pass).
+//
+// Every output of a geodesic step is a copy of exactly one input value: the
+// extremal pixel of the clipped 3x3 window (Eq. 1-2) or the mask (Eq. 3).
+// The forward kernel records, per step and pixel, a code naming that source:
+//   code (dy+1)*3 + (dx+1)  the FIRST extremal neighbour in raster (dy, dx)
+//                           order (ties between neighbours go to the earlier
+//                           one, as max_pool2d's indices do);
+//   code 9                  the mask won the clamp (ties go to the mask).
+// The first extremum in raster order is what a row pass followed by a column
+// pass yields when each keeps its earliest extremum on ties (the 3x3 square
+// decomposes as in Section 3.1).  The backward kernel is a GATHER: pixel q
+// collects the upstream gradient of every neighbour p whose code points at
+// q, visiting p in raster order (the order a raster-order scatter delivers
+// them), and the mask gradient collects g(q) where code(q) == 9.
+//
+// Both kernels are temporal-blocked: up to GB_K steps per launch on a 64 x 64
+// tile with a GB_K-pixel halo held in LDS.
+//
+//   block_codes_kernel  k steps forward; codes of the core pixels are staged
+//                       in LDS and stored as 16-byte rows;
+//   block_bwd_kernel    k steps backward; the mask gradient is accumulated in
+//                       registers starting from the stored value, so its
+//                       additions happen in the same order (steps from last to
+//                       first) as in a one-step-at-a-time reverse pass.
+//
+// Values must be finite: a pixel outside the image is represented by the
+// neutral extremum (-inf for dilation), which must never tie with a real
+// value.  Codes are stored densely: codes[image][step][y][width] bytes.
+//
+// Layout: lane = region column (64 per region), wave w = region rows
+// [8w, 8w + 8).  Each lane walks its 8 rows keeping the row-pass results (or
+// codes and gradients) of three rows on a rolling window, so a step costs
+// three LDS reads per pixel and array.  After step s of k only the band
+// within k-1-s of the core is still needed; waves outside it skip.  One
+// launch covers a batch of images (grid.z = image).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "chain_block.hpp"
+
+namespace geochain {
+
+constexpr uint8_t CODE_MASK = 9;
+constexpr uint8_t CODE_NONE = 255;
+
+template <int OP, typename T>
+__device__ __forceinline__ bool better(T a, T b) {
+    return OP == OP_DILATE ? (a > b) : (a < b);
+}
+
+// Region: GB_RW = 64 columns, one per lane; wave w holds rows [8w, 8w + 8).
+// Core: (64 - 2 GB_K) columns by (rows - 2 GB_K) rows.  Every wave walks the
+// same rows in the same order, so band tests are uniform per wave.
+constexpr int GB_K = 8;                        // largest steps per launch
+constexpr int GB_RW = 64;                      // region width (lanes)
+constexpr int GB_CX = GB_RW - 2 * GB_K;        // core width (48)
+constexpr int GB_WR = 8;                       // rows per wave
+
+template <typename T> struct GradTile {
+    // f64 tiles are shorter so that two state planes and the codes fit LDS.
+    static constexpr int NW = sizeof(T) == 8 ? 12 : 16;   // waves
+    static constexpr int RH = NW * GB_WR;                 // region height
+    static constexpr int CY = RH - 2 * GB_K;              // core height
+    static constexpr int THREADS = 64 * NW;
+};
+
+struct GradBlockArgs {
+    const void *src;          // state (codes kernel) or upstream gradient (bwd) at the block's start
+    const void *mask;         // mask (codes kernel)
+    void *dst;                // state / gradient at the block's end
+    void *g_mask;             // bwd: mask gradient, accumulated
+    uint8_t *codes;           // codes of the block's first step, image 0
+    int64_t codes_step;       // bytes between steps (height * width)
+    int64_t codes_image;      // bytes between images (n_steps * height * width)
+    int64_t image_stride;     // elements between images of src / mask / dst / g_mask
+    int64_t pitch;
+    int32_t width, height;
+    int32_t k;                // steps in this launch (<= GB_K)
+};
+
+// Stores one step's core codes (GB_CX x CY bytes staged in LDS) as 16-byte
+// pieces: 3 threads per row.
+template <int CY>
+__device__ __forceinline__ void gb_store_codes(const uint8_t (*sc)[GB_CX], uint8_t *codes, int x0, int y0,
+                                               int width, int height) {
+    const int row = threadIdx.x / 3, seg = (threadIdx.x % 3) * 16;
+    if (row >= CY) return;
+    const int y = y0 + row, x = x0 + seg;
+    if (y >= height || x >= width) return;
+    uint8_t *p = codes + (int64_t)y * width + x;
+    if (x + 16 <= width && ((uintptr_t)p & 15) == 0) {
+        *reinterpret_cast<uint4 *>(p) = *reinterpret_cast<const uint4 *>(&sc[row][seg]);
+    } else {
+        for (int i = 0; i < 16 && x + i < width; ++i) p[i] = sc[row][seg + i];
+    }
+}
+
+template <typename T, int OP>
+__global__ __launch_bounds__(GradTile<T>::THREADS) void block_codes_kernel(GradBlockArgs a) {
+    using B = Bounds<T, OP>;
+    using G = GradTile<T>;
+    constexpr int RH = G::RH, CY = G::CY;
+    __shared__ T sf[2][RH][GB_RW];
+    __shared__ __attribute__((aligned(16))) uint8_t sc[CY][GB_CX];
+    const int img = blockIdx.z;
+    const T *src = static_cast<const T *>(a.src) + img * a.image_stride;
+    const T *msk = static_cast<const T *>(a.mask) + img * a.image_stride;
+    T *dst = static_cast<T *>(a.dst) + img * a.image_stride;
+    uint8_t *codes = a.codes + img * a.codes_image;
+    const int x0 = blockIdx.x * GB_CX, y0 = blockIdx.y * CY;  // core origin
+    const int rx0 = x0 - GB_K, ry0 = y0 - GB_K;               // region origin
+    const int x = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int xl = max(x - 1, 0), xr = min(x + 1, GB_RW - 1);  // edge lanes: harmless repeats
+    const int gx = rx0 + x;
+    const bool xin = (unsigned)gx < (unsigned)a.width;
+
+    // state plane 0 and the lane's mask rows
+    T m[GB_WR];
+#pragma unroll
+    for (int r = 0; r < GB_WR; ++r) {
+        const int ly = w * GB_WR + r, y = ry0 + ly;
+        const bool in = xin && (unsigned)y < (unsigned)a.height;
+        const int64_t off = (int64_t)y * a.pitch + gx;
+        sf[0][ly][x] = in ? src[off] : B::bottom();
+        m[r] = in ? msk[off] : B::bottom();
+    }
+    __syncthreads();
+
+    const int k = a.k;
+    int cur = 0;
+    for (int s = 0; s < k; ++s) {
+        const int lo = GB_K - (k - 1 - s), hi_r = GB_K + CY + (k - 1 - s);  // rows needed after this step
+        // A wave with any needed row computes all its rows: the others are
+        // never read again (their window rows are clamped into the tile).
+        if (w * GB_WR + GB_WR > lo && w * GB_WR < hi_r) {
+            // row pass (value, dx index) of rows y-1, y, y+1 on a rolling window
+            auto row_pass = [&](int ly, T &v, int &ix) {
+                v = sf[cur][ly][xl];
+                ix = 0;
+                const T c = sf[cur][ly][x], r = sf[cur][ly][xr];
+                if (better<OP>(c, v)) { v = c; ix = 1; }
+                if (better<OP>(r, v)) { v = r; ix = 2; }
+            };
+            T h0, h1, h2;
+            int i0, i1, i2;
+            row_pass(max(w * GB_WR - 1, 0), h0, i0);
+            row_pass(w * GB_WR, h1, i1);
+#pragma unroll
+            for (int r = 0; r < GB_WR; ++r) {
+                const int y = w * GB_WR + r;
+                row_pass(min(y + 1, RH - 1), h2, i2);
+                T best = h0;
+                int code = i0;
+                if (better<OP>(h1, best)) { best = h1; code = 3 + i1; }
+                if (better<OP>(h2, best)) { best = h2; code = 6 + i2; }
+                const bool mask_wins = OP == OP_DILATE ? !(best < m[r]) : !(best > m[r]);
+                sf[cur ^ 1][y][x] = mask_wins ? m[r] : best;
+                const int cy = y - GB_K, cx = x - GB_K;
+                if ((unsigned)cy < (unsigned)CY && (unsigned)cx < (unsigned)GB_CX)
+                    sc[cy][cx] = mask_wins ? CODE_MASK : (uint8_t)code;
+                h0 = h1; i0 = i1;
+                h1 = h2; i1 = i2;
+            }
+        }
+        __syncthreads();
+        gb_store_codes<CY>(sc, codes + s * a.codes_step, x0, y0, a.width, a.height);
+        cur ^= 1;
+        __syncthreads();
+    }
+    // core of the final state
+    if ((unsigned)(x - GB_K) < (unsigned)GB_CX && xin) {
+#pragma unroll
+        for (int r = 0; r < GB_WR; ++r) {
+            const int ly = w * GB_WR + r, y = ry0 + ly;
+            if ((unsigned)(ly - GB_K) < (unsigned)CY && y < a.height) dst[(int64_t)y * a.pitch + gx] = sf[cur][ly][x];
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(GradTile<T>::THREADS) void block_bwd_kernel(GradBlockArgs a) {
+    using G = GradTile<T>;
+    constexpr int RH = G::RH, CY = G::CY;
+    __shared__ T sg[2][RH][GB_RW];
+    __shared__ __attribute__((aligned(16))) uint8_t scd[GB_K][RH][GB_RW];
+    const int img = blockIdx.z;
+    const T *gin = static_cast<const T *>(a.src) + img * a.image_stride;
+    T *gout = static_cast<T *>(a.dst) + img * a.image_stride;
+    T *gm = static_cast<T *>(a.g_mask) + img * a.image_stride;
+    const uint8_t *codes = a.codes + img * a.codes_image;
+    const int x0 = blockIdx.x * GB_CX, y0 = blockIdx.y * CY;
+    const int rx0 = x0 - GB_K, ry0 = y0 - GB_K;
+    const int x = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int xl = max(x - 1, 0), xr = min(x + 1, GB_RW - 1);
+    const int gx = rx0 + x;
+    const bool xin = (unsigned)gx < (unsigned)a.width;
+    const int k = a.k;
+
+    // gradient plane 0; codes of the k steps (words where the region is
+    // inside the image and aligned, else bytes)
+#pragma unroll
+    for (int r = 0; r < GB_WR; ++r) {
+        const int ly = w * GB_WR + r, y = ry0 + ly;
+        const bool in = xin && (unsigned)y < (unsigned)a.height;
+        sg[0][ly][x] = in ? gin[(int64_t)y * a.pitch + gx] : T(0);
+    }
+    const bool inside = rx0 >= 0 && ry0 >= 0 && rx0 + GB_RW <= a.width && ry0 + RH <= a.height &&
+                        (a.width & 3) == 0 && (((uintptr_t)codes + rx0) & 3) == 0 && (a.codes_step & 3) == 0;
+    if (inside) {
+        constexpr int WPR = GB_RW / 4;
+        for (int i = threadIdx.x; i < k * RH * WPR; i += G::THREADS) {
+            const int s = i / (RH * WPR), rem = i % (RH * WPR);
+            const int ly = rem / WPR, lw = rem % WPR;
+            *reinterpret_cast<uint32_t *>(&scd[s][ly][4 * lw]) = *reinterpret_cast<const uint32_t *>(
+                codes + s * a.codes_step + (int64_t)(ry0 + ly) * a.width + rx0 + 4 * lw);
+        }
+    } else {
+        for (int i = threadIdx.x; i < k * RH * GB_RW; i += G::THREADS) {
+            const int s = i / (RH * GB_RW), rem = i % (RH * GB_RW);
+            const int ly = rem / GB_RW, lx = rem % GB_RW;
+            const int y = ry0 + ly, xx = rx0 + lx;
+            const bool in = (unsigned)y < (unsigned)a.height && (unsigned)xx < (unsigned)a.width;
+            scd[s][ly][lx] = in ? codes[s * a.codes_step + (int64_t)y * a.width + xx] : CODE_NONE;
+        }
+    }
+    // Mask-gradient accumulators of the lane's rows, starting from the
+    // stored value so the additions keep the one-step-at-a-time order.
+    const bool col_core = (unsigned)(x - GB_K) < (unsigned)GB_CX && xin;
+    T acc[GB_WR];
+#pragma unroll
+    for (int r = 0; r < GB_WR; ++r) {
+        const int ly = w * GB_WR + r, y = ry0 + ly;
+        const bool in = col_core && (unsigned)(ly - GB_K) < (unsigned)CY && y < a.height;
+        acc[r] = in ? gm[(int64_t)y * a.pitch + gx] : T(0);
+    }
+    __syncthreads();
+
+    int cur = 0;
+    for (int s = k - 1; s >= 0; --s) {
+        const int lo = GB_K - s, hi_r = GB_K + CY + s;  // rows needed after this step
+        // As in the forward kernel: all rows of a wave or none.
+        if (w * GB_WR + GB_WR > lo && w * GB_WR < hi_r) {
+            // rolling window of (code, gradient) at columns x-1, x, x+1 of
+            // rows y-1, y, y+1
+            auto load_row = [&](int ly, uint8_t *c, T *g) {
+                c[0] = scd[s][ly][xl]; g[0] = sg[cur][ly][xl];
+                c[1] = scd[s][ly][x];  g[1] = sg[cur][ly][x];
+                c[2] = scd[s][ly][xr]; g[2] = sg[cur][ly][xr];
+            };
+            uint8_t c0[3], c1[3], c2[3];
+            T g0[3], g1[3], g2[3];
+            load_row(max(w * GB_WR - 1, 0), c0, g0);
+            load_row(w * GB_WR, c1, g1);
+#pragma unroll
+            for (int r = 0; r < GB_WR; ++r) {
+                const int y = w * GB_WR + r;
+                load_row(min(y + 1, RH - 1), c2, g2);
+                // neighbour p = q + d, d in raster order j; it sent to q iff
+                // its code is 8 - j
+                T sum = T(0);
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    if (c0[d] == 8 - d) sum += g0[d];
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    if (c1[d] == 5 - d) sum += g1[d];
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    if (c2[d] == 2 - d) sum += g2[d];
+                sg[cur ^ 1][y][x] = sum;
+                if (c1[1] == CODE_MASK) acc[r] += g1[1];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    c0[d] = c1[d]; g0[d] = g1[d];
+                    c1[d] = c2[d]; g1[d] = g2[d];
+                }
+            }
+        }
+        cur ^= 1;
+        __syncthreads();
+    }
+    // gradient w.r.t. the state before the block, and the mask gradient
+#pragma unroll
+    for (int r = 0; r < GB_WR; ++r) {
+        const int ly = w * GB_WR + r, y = ry0 + ly;
+        if (col_core && (unsigned)(ly - GB_K) < (unsigned)CY && y < a.height) {
+            gout[(int64_t)y * a.pitch + gx] = sg[cur][ly][x];
+            gm[(int64_t)y * a.pitch + gx] = acc[r];
+        }
+    }
+}
+
+}  // namespace geochain
