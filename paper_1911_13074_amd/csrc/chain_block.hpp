@@ -42,6 +42,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace geochain {
 
 enum : int { OP_DILATE = 0, OP_ERODE = 1 };
@@ -263,73 +265,84 @@ __device__ __forceinline__ uint32_t chain_block_body(const BlockArgs &a, int rx0
     const int busy_b = halo + a.core_y + k - w * RPW;          // s < busy_b
     const int busy = __builtin_amdgcn_readfirstlane(max(0, min(k, min(busy_a, busy_b))));
 
-    for (int s = 0; s < busy; ++s) {
-        // ---- 1. row pass ----
-        R h[RPW][CW];
+    // Only waves holding core rows track changes; the others run the same
+    // steps without the comparisons (one loop per case, each branch-free).
+    const bool wave_has_core = DETECT && w * RPW + RPW > halo && w * RPW < halo + a.core_y;
+    auto run_steps = [&](auto detect_tag) {
+        constexpr bool D = decltype(detect_tag)::value;
+        for (int s = 0; s < busy; ++s) {
+            // ---- 1. row pass ----
+            R h[RPW][CW];
 #pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-            const R left = lane_shift<DPP_WAVE_SHR1>(v[r][CW - 1]);
-            const R right = lane_shift<DPP_WAVE_SHL1>(v[r][0]);
-            if constexpr (CW == 1) {
-                h[r][0] = P::pick(P::pick(left, v[r][0]), right);
-            } else if constexpr (CW == 2) {
-                // The pair's own extremum is shared by both outputs; each
-                // output then takes one cross-lane neighbour, which the
-                // compiler folds into a single DPP-sourced max/min.
-                const R t = P::pick(v[r][0], v[r][1]);
-                h[r][0] = P::pick(t, left);
-                h[r][1] = P::pick(t, right);
-            } else {
+            for (int r = 0; r < RPW; ++r) {
+                const R left = lane_shift<DPP_WAVE_SHR1>(v[r][CW - 1]);
+                const R right = lane_shift<DPP_WAVE_SHL1>(v[r][0]);
+                if constexpr (CW == 1) {
+                    h[r][0] = P::pick(P::pick(left, v[r][0]), right);
+                } else if constexpr (CW == 2) {
+                    // The pair's own extremum is shared by both outputs; each
+                    // output then takes one cross-lane neighbour, which the
+                    // compiler folds into a single DPP-sourced max/min.
+                    const R t = P::pick(v[r][0], v[r][1]);
+                    h[r][0] = P::pick(t, left);
+                    h[r][1] = P::pick(t, right);
+                } else {
 #pragma unroll
-                for (int c = 0; c < CW; ++c) {
-                    const R l = c == 0 ? left : v[r][c - 1];
-                    const R rr = c == CW - 1 ? right : v[r][c + 1];
-                    h[r][c] = P::pick(P::pick(v[r][c], rr), l);
+                    for (int c = 0; c < CW; ++c) {
+                        const R l = c == 0 ? left : v[r][c - 1];
+                        const R rr = c == CW - 1 ? right : v[r][c + 1];
+                        h[r][c] = P::pick(P::pick(v[r][c], rr), l);
+                    }
                 }
             }
-        }
-        // ---- 2. exchange edge rows with the waves above and below ----
-        const int par = s & 1;
-#pragma unroll
-        for (int c = 0; c < CW; ++c) {
-            xch[par][w][0][lane * CW + c] = h[0][c];
-            xch[par][w][1][lane * CW + c] = h[RPW - 1][c];
-        }
-        __syncthreads();
-        // The first (last) wave has no wave above (below); it reads its own
-        // opposite edge instead, a wrong but harmless value on the region's
-        // outer edge.  Branch-free, so the whole step is one basic block.
-        const int wa = w > 0 ? w - 1 : NW - 1;
-        const int wb = w < NW - 1 ? w + 1 : 0;
-        R above[CW], below[CW];
-#pragma unroll
-        for (int c = 0; c < CW; ++c) {
-            above[c] = xch[par][wa][1][lane * CW + c];
-            below[c] = xch[par][wb][0][lane * CW + c];
-        }
-        // ---- 3. column pass + clamp ----
-        uint64_t changed = 0;
-#pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-            const int ry = w * RPW + r;
-            const bool row_in_core = DETECT && ry >= halo && ry < halo + a.core_y && ry0 + ry < a.height;
+            // ---- 2. exchange edge rows with the waves above and below ----
+            const int par = s & 1;
 #pragma unroll
             for (int c = 0; c < CW; ++c) {
-                const R up = r == 0 ? above[c] : h[r - 1][c];
-                const R dn = r == RPW - 1 ? below[c] : h[r + 1][c];
-                R nv = P::pick(P::pick(up, h[r][c]), dn);
-                if constexpr (CLAMP) nv = P::clamp(nv, m[r][c]);
-                if constexpr (DETECT) {
-                    if (row_in_core)
-                        changed |= __builtin_amdgcn_ballot_w64(nv != v[r][c]) & col_in_core[c];
+                xch[par][w][0][lane * CW + c] = h[0][c];
+                xch[par][w][1][lane * CW + c] = h[RPW - 1][c];
+            }
+            __syncthreads();
+            // The first (last) wave has no wave above (below); it reads its own
+            // opposite edge instead, a wrong but harmless value on the region's
+            // outer edge.  Branch-free, so the whole step is one basic block.
+            const int wa = w > 0 ? w - 1 : NW - 1;
+            const int wb = w < NW - 1 ? w + 1 : 0;
+            R above[CW], below[CW];
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                above[c] = xch[par][wa][1][lane * CW + c];
+                below[c] = xch[par][wb][0][lane * CW + c];
+            }
+            // ---- 3. column pass + clamp ----
+            uint64_t changed = 0;
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                const int ry = w * RPW + r;
+                const bool row_in_core = D && ry >= halo && ry < halo + a.core_y && ry0 + ry < a.height;
+#pragma unroll
+                for (int c = 0; c < CW; ++c) {
+                    const R up = r == 0 ? above[c] : h[r - 1][c];
+                    const R dn = r == RPW - 1 ? below[c] : h[r + 1][c];
+                    R nv = P::pick(P::pick(up, h[r][c]), dn);
+                    if constexpr (CLAMP) nv = P::clamp(nv, m[r][c]);
+                    if constexpr (D) {
+                        // branch-free: a uniform row mask instead of an if
+                        const uint64_t row_mask = row_in_core ? ~0ull : 0ull;
+                        changed |= __builtin_amdgcn_ballot_w64(nv != v[r][c]) & col_in_core[c] & row_mask;
+                    }
+                    v[r][c] = nv;
                 }
-                v[r][c] = nv;
+            }
+            if constexpr (D) {
+                if (changed) step_bits |= 1u << s;
             }
         }
-        if constexpr (DETECT) {
-            if (changed) step_bits |= 1u << s;
-        }
-    }
+    };
+    if (wave_has_core)
+        run_steps(std::true_type{});
+    else
+        run_steps(std::false_type{});
     for (int s = busy; s < k; ++s) __syncthreads();
 
     // ---- store the core ----
@@ -466,66 +479,74 @@ __device__ __forceinline__ uint32_t chain_block_body_g2(const BlockArgs &a, int 
     const int above_w = grp ? w : wa, above_slot = grp ? 1 : 3;
     const int below_w = grp ? wb : w, below_slot = grp ? 0 : 2;
 
-    for (int s = 0; s < busy; ++s) {
-        // ---- 1. row pass ----
-        R h[RPW][CW];
+    const bool wave_has_core = DETECT && w * WR + WR > halo && w * WR < halo + a.core_y;
+    auto run_steps = [&](auto detect_tag) {
+        constexpr bool D = decltype(detect_tag)::value;
+        for (int s = 0; s < busy; ++s) {
+            // ---- 1. row pass ----
+            R h[RPW][CW];
 #pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-            const R left = lane_shift<DPP_WAVE_SHR1>(v[r][CW - 1]);
-            const R right = lane_shift<DPP_WAVE_SHL1>(v[r][0]);
-            if constexpr (CW == 3) {
-                // Both partial extrema feed two outputs each, so the
-                // compiler keeps them and folds the neighbour lanes into
-                // DPP-sourced max/min: 5 operations for 3 pixels.
-                const R t1 = P::pick(v[r][0], v[r][1]);
-                const R t2 = P::pick(v[r][1], v[r][2]);
-                h[r][0] = P::pick(t1, left);
-                h[r][1] = P::pick(t1, t2);
-                h[r][2] = P::pick(t2, right);
-            } else {
+            for (int r = 0; r < RPW; ++r) {
+                const R left = lane_shift<DPP_WAVE_SHR1>(v[r][CW - 1]);
+                const R right = lane_shift<DPP_WAVE_SHL1>(v[r][0]);
+                if constexpr (CW == 3) {
+                    // Both partial extrema feed two outputs each, so the
+                    // compiler keeps them and folds the neighbour lanes into
+                    // DPP-sourced max/min: 5 operations for 3 pixels.
+                    const R t1 = P::pick(v[r][0], v[r][1]);
+                    const R t2 = P::pick(v[r][1], v[r][2]);
+                    h[r][0] = P::pick(t1, left);
+                    h[r][1] = P::pick(t1, t2);
+                    h[r][2] = P::pick(t2, right);
+                } else {
 #pragma unroll
-                for (int c = 0; c < CW; ++c) {
-                    const R l = c == 0 ? left : v[r][c - 1];
-                    const R rr = c == CW - 1 ? right : v[r][c + 1];
-                    h[r][c] = P::pick(P::pick(v[r][c], rr), l);
+                    for (int c = 0; c < CW; ++c) {
+                        const R l = c == 0 ? left : v[r][c - 1];
+                        const R rr = c == CW - 1 ? right : v[r][c + 1];
+                        h[r][c] = P::pick(P::pick(v[r][c], rr), l);
+                    }
                 }
             }
-        }
-        // ---- 2. exchange through LDS ----
-        const int par = s & 1;
-#pragma unroll
-        for (int c = 0; c < CW; ++c) {
-            xch[par][w][grp * 2][lc * CW + c] = h[0][c];
-            xch[par][w][grp * 2 + 1][lc * CW + c] = h[RPW - 1][c];
-        }
-        __syncthreads();
-        R above[CW], below[CW];
-#pragma unroll
-        for (int c = 0; c < CW; ++c) {
-            above[c] = xch[par][above_w][above_slot][lc * CW + c];
-            below[c] = xch[par][below_w][below_slot][lc * CW + c];
-        }
-        // ---- 3. column pass + clamp ----
-        uint64_t changed = 0;
-#pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-            const int ry = row0 + r;
-            const bool row_in_core = DETECT && ry >= halo && ry < halo + a.core_y && ry0 + ry < a.height;
+            // ---- 2. exchange through LDS ----
+            const int par = s & 1;
 #pragma unroll
             for (int c = 0; c < CW; ++c) {
-                const R up = r == 0 ? above[c] : h[r - 1][c];
-                const R dn = r == RPW - 1 ? below[c] : h[r + 1][c];
-                R nv = P::pick(P::pick(up, h[r][c]), dn);
-                if constexpr (CLAMP) nv = P::clamp(nv, m[r][c]);
-                if constexpr (DETECT)
-                    changed |= __builtin_amdgcn_ballot_w64(row_in_core && nv != v[r][c]) & col_in_core[c];
-                v[r][c] = nv;
+                xch[par][w][grp * 2][lc * CW + c] = h[0][c];
+                xch[par][w][grp * 2 + 1][lc * CW + c] = h[RPW - 1][c];
+            }
+            __syncthreads();
+            R above[CW], below[CW];
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                above[c] = xch[par][above_w][above_slot][lc * CW + c];
+                below[c] = xch[par][below_w][below_slot][lc * CW + c];
+            }
+            // ---- 3. column pass + clamp ----
+            uint64_t changed = 0;
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                const int ry = row0 + r;
+                const bool row_in_core = D && ry >= halo && ry < halo + a.core_y && ry0 + ry < a.height;
+#pragma unroll
+                for (int c = 0; c < CW; ++c) {
+                    const R up = r == 0 ? above[c] : h[r - 1][c];
+                    const R dn = r == RPW - 1 ? below[c] : h[r + 1][c];
+                    R nv = P::pick(P::pick(up, h[r][c]), dn);
+                    if constexpr (CLAMP) nv = P::clamp(nv, m[r][c]);
+                    if constexpr (D)
+                        changed |= __builtin_amdgcn_ballot_w64(row_in_core && nv != v[r][c]) & col_in_core[c];
+                    v[r][c] = nv;
+                }
+            }
+            if constexpr (D) {
+                if (changed) step_bits |= 1u << s;
             }
         }
-        if constexpr (DETECT) {
-            if (changed) step_bits |= 1u << s;
-        }
-    }
+    };
+    if (wave_has_core)
+        run_steps(std::true_type{});
+    else
+        run_steps(std::false_type{});
     for (int s = busy; s < k; ++s) __syncthreads();
 
     // ---- store the core ----
