@@ -1,4 +1,5 @@
-"""CPU oracle for chains of elementary 3x3 geodesic dilations / erosions.
+"""CPU oracle for chains of elementary 3x3 geodesic dilations / erosions
+and the reconstruction-based operators built on them.
 
 TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
 benchmark's CPU-baseline leg.  The GPU library never imports or calls it.
@@ -172,3 +173,92 @@ def chain_vjp(op, f, m, n, g_out):
     """Gradient of sum(g_out * chain(op, f, n, m)) w.r.t. (f, m), float64."""
     _, codes = chain_codes(op, f, n, m)
     return chain_grad(codes, g_out)
+
+
+# --------------------------------------------------------------------------
+# Reconstruction-based operators (Section 2, Eq. 6-12), composed from the
+# reconstruction above and pixelwise arithmetic done in the image's dtype:
+#   - uint8 differences saturate at 0 (the paper leaves f - h undefined for
+#     8-bit images; the saturating reading keeps markers inside [0, 255]);
+#   - float32 / float64 differences are one IEEE subtraction in that dtype,
+#     with h first rounded to the dtype;
+#   - the border B of an image is its first and last row and column;
+#   - every operator returns (image, steps_changed, converged) of its one
+#     reconstruction; with a step cap that is reached, the operator is formed
+#     from the capped chain.
+# --------------------------------------------------------------------------
+def _check_image(f):
+    f = np.asarray(f)
+    _as_f64(f)
+    return f
+
+
+def _h_in_dtype(dtype, h):
+    h = float(h)
+    if not np.isfinite(h) or h < 0:
+        raise ValueError("h must be finite and >= 0")
+    if np.dtype(dtype) == np.uint8:
+        if h != int(h):
+            raise ValueError("h must be an integer for uint8 images")
+        return np.uint8(min(int(h), 255))
+    return np.dtype(dtype).type(h)
+
+
+def _sub_in_dtype(a, b):
+    """a - b in a's dtype: uint8 saturates at 0, floats round once."""
+    if a.dtype == np.uint8:
+        d = a.astype(np.int16) - np.asarray(b).astype(np.int16)
+        return np.maximum(d, 0).astype(np.uint8)
+    return np.subtract(a, b, dtype=a.dtype)
+
+
+def _border_marker(f, inner):
+    """f on the border B, the constant inner everywhere else (Eq. 9, 11)."""
+    m = np.full_like(f, inner)
+    m[0, :] = f[0, :]
+    m[-1, :] = f[-1, :]
+    m[:, 0] = f[:, 0]
+    m[:, -1] = f[:, -1]
+    return m
+
+
+def hmax(f, h, max_steps=-1):
+    """H-maxima (Eq. 6): reconstruction by dilation of f - h under f."""
+    f = _check_image(f)
+    return reconstruct(DILATE, _sub_in_dtype(f, _h_in_dtype(f.dtype, h)), f, max_steps)
+
+
+def dome(f, h, max_steps=-1):
+    """Dome extraction (Eq. 7): f - HMAX_h(f)."""
+    f = _check_image(f)
+    r, steps, conv = hmax(f, h, max_steps)
+    return _sub_in_dtype(f, r), steps, conv
+
+
+def hfill(f, max_steps=-1):
+    """Hole filling (Eq. 8-9): reconstruction by erosion, above the mask f,
+    of the marker that equals f on the border and max f inside."""
+    f = _check_image(f)
+    if f.size == 0:
+        return f.copy(), 0, True
+    return reconstruct(ERODE, _border_marker(f, f.max()), f, max_steps)
+
+
+def raobj(f, max_steps=-1):
+    """Removal of border objects (Eq. 10-11): f minus the reconstruction by
+    dilation, under f, of the marker that equals f on the border and min f
+    inside."""
+    f = _check_image(f)
+    if f.size == 0:
+        return f.copy(), 0, True
+    r, steps, conv = reconstruct(DILATE, _border_marker(f, f.min()), f, max_steps)
+    return _sub_in_dtype(f, r), steps, conv
+
+
+def open_by_reconstruction(f, s, max_steps=-1):
+    """Opening by reconstruction (Eq. 12): reconstruction by dilation, under
+    f, of eps_s(f) = s plain 3x3 erosions of f (Eq. 4 without a mask)."""
+    f = _check_image(f)
+    if s < 0:
+        raise ValueError("s must be >= 0")
+    return reconstruct(DILATE, chain(ERODE, f, int(s)), f, max_steps)
