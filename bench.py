@@ -204,6 +204,29 @@ def main():
         extra["reconstruction_by_dilation"] = {
             "steps_changed": rec_steps["n"], "ms": round(ms_r, 4),
             "gpx_steps_per_s": round(px * rec_steps["n"] / ms_r / 1e6, 2)}
+        # Reconstruction-based operators (Eq. 6-12) on the 1024^2 u8 image:
+        # one reconstruction each, plus marker / difference passes.
+        fo = torch.from_numpy(workloads.operator_u8(size=S)).to(dev)
+        oo = torch.empty_like(fo)
+        op_runs = (("hmax_40", 0, lambda: gc.hmax(fo, 40, out=oo)),
+                   ("dome_40", 0, lambda: gc.dome(fo, 40, out=oo)),
+                   ("hfill", 0, lambda: gc.hfill(fo, out=oo)),
+                   ("raobj", 0, lambda: gc.raobj(fo, out=oo)),
+                   ("open_rec_5", 5, lambda: gc.open_by_reconstruction(fo, 5, out=oo)),
+                   ("open_rec_75", 75, lambda: gc.open_by_reconstruction(fo, 75, out=oo)))
+        ops_extra = {}
+        for name, pre, fn in op_runs:
+            got = {}
+
+            def run_op():
+                got["steps"] = fn()[1]
+
+            ms_o = timed(run_op, max(3, args.steps // 4), 1)
+            chain_len = pre + got["steps"]
+            ops_extra[name] = {"steps_changed": got["steps"], "chain_steps": chain_len, "ms": round(ms_o, 4),
+                               "gpx_steps_per_s": round(px * chain_len / ms_o / 1e6, 2)}
+        extra["operators_1024_u8"] = ops_extra
+        del fo, oo
         # Batched: 64 uneven images in one persistent graph-recorded launch.
         batch = workloads.batch_u8()
         items = [(torch.from_numpy(it.marker).to(dev), torch.from_numpy(it.mask).to(dev), it.n_steps)

@@ -123,6 +123,45 @@ int gc_reconstruct_by_erosion(gc_dtype dtype, const void *marker, const void *ma
                               int64_t *steps_out, void *hip_stream);
 
 /* ---------------------------------------------------------------------
+ * Reconstruction-based operators (Section 2, Eq. 6-12).
+ *
+ * Each runs ONE reconstruction with f as the mask, framed by pixelwise
+ * passes; f is read-only and out receives the result (out must not overlap
+ * f: GC_ERR_ALIAS).  Pixelwise arithmetic is done in the image's dtype:
+ * u8 differences saturate at 0, f32/f64 differences are one IEEE
+ * subtraction (h is first rounded to the dtype).  The border B of an image
+ * is its first and last row and column.
+ *
+ * max_steps, *steps_out, GC_ERR_NOT_CONVERGED and the stream
+ * synchronisation are those of the reconstruction calls above; when the cap
+ * is reached the operator is formed from the capped chain and the status is
+ * GC_ERR_NOT_CONVERGED.
+ *
+ *   gc_hmax   H-maxima (Eq. 6): reconstruction by dilation of f - h under f.
+ *             h finite and >= 0; for u8 an integer (values above 255 act
+ *             as 255).
+ *   gc_dome   dome extraction (Eq. 7): f - HMAX_h(f).
+ *   gc_hfill  hole filling (Eq. 8-9): reconstruction by erosion, above f, of
+ *             the marker equal to f on B and to max f elsewhere.
+ *   gc_raobj  removal of objects touching the border (Eq. 10-11): f minus
+ *             the reconstruction by dilation, under f, of the marker equal
+ *             to f on B and to min f elsewhere.
+ *   gc_open_by_reconstruction  (Eq. 12): reconstruction by dilation, under
+ *             f, of size plain 3x3 erosions of f (size >= 0).
+ * ------------------------------------------------------------------- */
+int gc_hmax(gc_dtype dtype, const void *f, void *out, gc_shape shape, double h,
+            int64_t max_steps, int64_t *steps_out, void *hip_stream);
+int gc_dome(gc_dtype dtype, const void *f, void *out, gc_shape shape, double h,
+            int64_t max_steps, int64_t *steps_out, void *hip_stream);
+int gc_hfill(gc_dtype dtype, const void *f, void *out, gc_shape shape,
+             int64_t max_steps, int64_t *steps_out, void *hip_stream);
+int gc_raobj(gc_dtype dtype, const void *f, void *out, gc_shape shape,
+             int64_t max_steps, int64_t *steps_out, void *hip_stream);
+int gc_open_by_reconstruction(gc_dtype dtype, const void *f, void *out, gc_shape shape,
+                              int64_t size, int64_t max_steps, int64_t *steps_out,
+                              void *hip_stream);
+
+/* ---------------------------------------------------------------------
  * Batches: many independent chains (Eq. 4), each with its own image size
  * and number of steps, run by ONE persistent kernel launch recorded in a
  * HIP graph.  There is no batching in the paper; its closest analogue is

@@ -12,11 +12,16 @@ from .ops import (  # noqa: F401
     autotune,
     autotune_clear,
     dilate_chain,
+    dome,
     erode_chain,
     geodesic_chain_bwd,
     geodesic_chain_fwd_codes,
     geodesic_dilate_chain,
     geodesic_erode_chain,
+    hfill,
+    hmax,
+    open_by_reconstruction,
+    raobj,
     reconstruct_by_dilation,
     reconstruct_by_erosion,
     set_tuning,

@@ -54,6 +54,11 @@ SIGNATURES = {
     "gc_erode_chain": (ctypes.c_int, [_DT, _VP, _VP, gc_shape, _I64, _VP]),
     "gc_reconstruct_by_dilation": (ctypes.c_int, [_DT, _VP, _VP, _VP, gc_shape, _I64, _P_I64, _VP]),
     "gc_reconstruct_by_erosion": (ctypes.c_int, [_DT, _VP, _VP, _VP, gc_shape, _I64, _P_I64, _VP]),
+    "gc_hmax": (ctypes.c_int, [_DT, _VP, _VP, gc_shape, ctypes.c_double, _I64, _P_I64, _VP]),
+    "gc_dome": (ctypes.c_int, [_DT, _VP, _VP, gc_shape, ctypes.c_double, _I64, _P_I64, _VP]),
+    "gc_hfill": (ctypes.c_int, [_DT, _VP, _VP, gc_shape, _I64, _P_I64, _VP]),
+    "gc_raobj": (ctypes.c_int, [_DT, _VP, _VP, gc_shape, _I64, _P_I64, _VP]),
+    "gc_open_by_reconstruction": (ctypes.c_int, [_DT, _VP, _VP, gc_shape, _I64, _I64, _P_I64, _VP]),
     "gc_set_tuning": (ctypes.c_int, [_I32, _I32]),
     "gc_plan_create": (ctypes.c_int, [_DT, _DT, ctypes.POINTER(gc_item), _I32,
                                       ctypes.POINTER(ctypes.c_void_p)]),

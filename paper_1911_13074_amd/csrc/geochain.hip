@@ -21,6 +21,7 @@
 #include "chain_block.hpp"
 #include "persistent.hpp"
 #include "grad_block.hpp"
+#include "operators.hpp"
 
 namespace geochain {
 
@@ -186,6 +187,7 @@ struct Workspace {
     uint32_t *words = nullptr;      // device change words
     uint32_t *host_words = nullptr; // pinned mirror
     size_t nwords = 0;
+    void *partials = nullptr;       // PARTIALS_MAX per-workgroup extrema (operators)
 };
 
 static std::mutex g_ws_mu;
@@ -229,6 +231,23 @@ static int get_workspace(void *stream, size_t bytes, size_t nwords, Workspace **
         w.nwords = nwords;
     }
     *out = &w;
+    return GC_OK;
+}
+
+// Per-(device, stream) buffer of PARTIALS_MAX doubles for the extremum pass.
+static int get_partials(void *stream, void **out) {
+    int dev = 0;
+    GC_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(g_ws_mu);
+    Workspace &w = g_ws[{dev, stream}];
+    if (!w.partials) {
+        if (hipMalloc(&w.partials, PARTIALS_MAX * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            w.partials = nullptr;
+            return fail(GC_ERR_NO_MEMORY, "extremum partials");
+        }
+    }
+    *out = w.partials;
     return GC_OK;
 }
 
@@ -537,6 +556,97 @@ static int run_reconstruct(gc_dtype dtype, int op, const void *marker, const voi
     if (!converged) return fail(GC_ERR_NOT_CONVERGED, "reconstruction did not converge in %lld steps",
                                 (long long)max_steps);
     return GC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// reconstruction-based operators (Eq. 6-12)
+// ---------------------------------------------------------------------------
+enum { GOP_HMAX = 0, GOP_DOME = 1, GOP_HFILL = 2, GOP_RAOBJ = 3, GOP_OPEN_REC = 4 };
+
+// 16-byte chunks need every row start of every image aligned to 16 bytes.
+static bool rows_aligned16(const gc_shape &s, size_t es, const void *a, const void *b) {
+    return (s.pitch * (int64_t)es) % 16 == 0 && (uintptr_t)a % 16 == 0 && (uintptr_t)b % 16 == 0;
+}
+
+template <typename T>
+static PixelArgs<T> pixel_args(const gc_shape &s, const T *a, const T *b, T *out, bool vec) {
+    PixelArgs<T> p{};
+    p.a = a;
+    p.b = b;
+    p.out = out;
+    p.width = (int32_t)s.width;
+    p.height = (int32_t)s.height;
+    p.pitch = s.pitch;
+    const int64_t V = vec ? 16 / (int64_t)sizeof(T) : 1;
+    p.chunks_per_row = (s.width + V - 1) / V;
+    p.n_chunks = p.chunks_per_row * s.height;
+    return p;
+}
+
+static int px_grid(int64_t n_chunks, int64_t cap) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>((n_chunks + PX_THREADS - 1) / PX_THREADS, cap));
+}
+
+template <typename T, int KIND, int OP>
+static void px_launch(const PixelArgs<T> &p, bool vec, hipStream_t st) {
+    const int grid = px_grid(p.n_chunks, 4096);
+    if (vec)
+        hipLaunchKernelGGL((pixel_kernel<T, KIND, OP, true>), dim3(grid), dim3(PX_THREADS), 0, st, p);
+    else
+        hipLaunchKernelGGL((pixel_kernel<T, KIND, OP, false>), dim3(grid), dim3(PX_THREADS), 0, st, p);
+}
+
+// Writes one extremum per workgroup to p.out; returns how many.
+template <typename T, int OP>
+static int extremum_launch(const PixelArgs<T> &p, bool vec, hipStream_t st) {
+    const int grid = px_grid(p.n_chunks, PARTIALS_MAX);
+    if (vec)
+        hipLaunchKernelGGL((extremum_kernel<T, OP, true>), dim3(grid), dim3(PX_THREADS), 0, st, p);
+    else
+        hipLaunchKernelGGL((extremum_kernel<T, OP, false>), dim3(grid), dim3(PX_THREADS), 0, st, p);
+    return grid;
+}
+
+// Marker pass, one reconstruction with f as the mask, and for DOME / RAOBJ
+// the final difference f - rec.  out holds the marker, then the result.
+template <typename T>
+static int run_operator_t(gc_dtype dtype, int which, const T *f, T *out, const gc_shape &s, T h,
+                          int64_t size, int64_t max_steps, int64_t *steps_out, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const bool vec = rows_aligned16(s, sizeof(T), f, out);
+    int rec_op = OP_DILATE;
+    if (which == GOP_HMAX || which == GOP_DOME) {
+        PixelArgs<T> p = pixel_args<T>(s, f, nullptr, out, vec);
+        p.h = h;
+        px_launch<T, PX_SUB_SCALAR, OP_DILATE>(p, vec, st);
+        GC_HIP(hipGetLastError());
+    } else if (which == GOP_HFILL || which == GOP_RAOBJ) {
+        void *partials = nullptr;
+        int rc = get_partials(stream, &partials);
+        if (rc != GC_OK) return rc;
+        const PixelArgs<T> pe = pixel_args<T>(s, f, nullptr, (T *)partials, vec);
+        PixelArgs<T> pb = pixel_args<T>(s, f, nullptr, out, vec);
+        pb.partials = (const T *)partials;
+        if (which == GOP_HFILL) {
+            pb.n_partials = extremum_launch<T, OP_DILATE>(pe, vec, st);
+            px_launch<T, PX_BORDER, OP_DILATE>(pb, vec, st);
+            rec_op = OP_ERODE;
+        } else {
+            pb.n_partials = extremum_launch<T, OP_ERODE>(pe, vec, st);
+            px_launch<T, PX_BORDER, OP_ERODE>(pb, vec, st);
+        }
+        GC_HIP(hipGetLastError());
+    } else {
+        int rc = run_chain(dtype, OP_ERODE, MODE_PLAIN, f, nullptr, out, s, size, stream);
+        if (rc != GC_OK) return rc;
+    }
+    const int rrc = run_reconstruct(dtype, rec_op, out, f, out, s, max_steps, steps_out, stream);
+    if (rrc != GC_OK && rrc != GC_ERR_NOT_CONVERGED) return rrc;
+    if (which == GOP_DOME || which == GOP_RAOBJ) {
+        px_launch<T, PX_SUB_IMAGE, OP_DILATE>(pixel_args<T>(s, f, out, out, vec), vec, st);
+        GC_HIP(hipGetLastError());
+    }
+    return rrc;
 }
 
 // ---------------------------------------------------------------------------
@@ -1192,6 +1302,64 @@ int gc_reconstruct_by_erosion(gc_dtype dtype, const void *marker, const void *ma
                               gc_shape shape, int64_t max_steps, int64_t *steps_out,
                               void *hip_stream) {
     return reconstruct(dtype, OP_ERODE, marker, mask, out, shape, max_steps, steps_out, hip_stream);
+}
+
+static int geodesic_operator(gc_dtype dtype, int which, const void *f, void *out, gc_shape shape, double h,
+                             int64_t size, int64_t max_steps, int64_t *steps_out, void *stream) {
+    g_last_error.clear();
+    if (steps_out) *steps_out = 0;
+    int rc = validate_shape(dtype, shape);
+    if (rc != GC_OK) return rc;
+    const bool empty = shape.width == 0 || shape.height == 0;
+    if (!empty && (!f || !out)) return fail(GC_ERR_INVALID_ARG, "null image pointer");
+    const size_t es = elem_size(dtype);
+    if (!empty && overlap(extent(out, shape, es), extent(f, shape, es)))
+        return fail(GC_ERR_ALIAS, "out overlaps f (f is the mask of the reconstruction)");
+    if (which == GOP_HMAX || which == GOP_DOME) {
+        if (!std::isfinite(h) || h < 0) return fail(GC_ERR_INVALID_ARG, "h must be finite and >= 0");
+        if (dtype == GC_U8 && h != std::floor(h))
+            return fail(GC_ERR_INVALID_ARG, "h must be an integer for u8 images");
+    }
+    if (which == GOP_OPEN_REC && size < 0) return fail(GC_ERR_INVALID_ARG, "size < 0");
+    if (empty) return GC_OK;
+    switch (dtype) {
+        case GC_U8:
+            return run_operator_t<uint8_t>(dtype, which, (const uint8_t *)f, (uint8_t *)out, shape,
+                                           (uint8_t)std::min(h, 255.0), size, max_steps, steps_out, stream);
+        case GC_F32:
+            return run_operator_t<float>(dtype, which, (const float *)f, (float *)out, shape, (float)h, size,
+                                         max_steps, steps_out, stream);
+        case GC_F64:
+            return run_operator_t<double>(dtype, which, (const double *)f, (double *)out, shape, h, size,
+                                          max_steps, steps_out, stream);
+    }
+    return fail(GC_ERR_INVALID_ARG, "unknown dtype");
+}
+
+int gc_hmax(gc_dtype dtype, const void *f, void *out, gc_shape shape, double h, int64_t max_steps,
+            int64_t *steps_out, void *hip_stream) {
+    return geodesic_operator(dtype, GOP_HMAX, f, out, shape, h, 0, max_steps, steps_out, hip_stream);
+}
+
+int gc_dome(gc_dtype dtype, const void *f, void *out, gc_shape shape, double h, int64_t max_steps,
+            int64_t *steps_out, void *hip_stream) {
+    return geodesic_operator(dtype, GOP_DOME, f, out, shape, h, 0, max_steps, steps_out, hip_stream);
+}
+
+int gc_hfill(gc_dtype dtype, const void *f, void *out, gc_shape shape, int64_t max_steps,
+             int64_t *steps_out, void *hip_stream) {
+    return geodesic_operator(dtype, GOP_HFILL, f, out, shape, 0.0, 0, max_steps, steps_out, hip_stream);
+}
+
+int gc_raobj(gc_dtype dtype, const void *f, void *out, gc_shape shape, int64_t max_steps,
+             int64_t *steps_out, void *hip_stream) {
+    return geodesic_operator(dtype, GOP_RAOBJ, f, out, shape, 0.0, 0, max_steps, steps_out, hip_stream);
+}
+
+int gc_open_by_reconstruction(gc_dtype dtype, const void *f, void *out, gc_shape shape, int64_t size,
+                              int64_t max_steps, int64_t *steps_out, void *hip_stream) {
+    return geodesic_operator(dtype, GOP_OPEN_REC, f, out, shape, 0.0, size, max_steps, steps_out,
+                             hip_stream);
 }
 
 int gc_geodesic_chain_fwd_codes(gc_dtype dtype, gc_op op, const void *marker, const void *mask, void *out,

@@ -136,6 +136,48 @@ def reconstruct_by_erosion(marker, mask, max_steps=-1, out=None, allow_not_conve
                         allow_not_converged)
 
 
+def _operator(fn_name, f, extra, max_steps, out, allow_not_converged):
+    _check_image(f, "f")
+    out = _out_like(f, out)
+    steps = ctypes.c_int64(0)
+    with torch.cuda.device(f.device):
+        st = getattr(abi, fn_name)(_dtype_code(f), _ptr(f), _ptr(out), _shape(f), *extra,
+                                   int(max_steps), ctypes.byref(steps), _stream(f))
+    if st == abi.GC_ERR_NOT_CONVERGED and allow_not_converged:
+        return out, int(steps.value), False
+    abi.check(st, fn_name)
+    return out, int(steps.value), True
+
+
+def hmax(f, h, max_steps=-1, out=None, allow_not_converged=False):
+    """H-maxima (Eq. 6): reconstruction by dilation of f - h under f.
+    Returns (image, steps_changed, converged); synchronises the stream."""
+    return _operator("gc_hmax", f, (float(h),), max_steps, out, allow_not_converged)
+
+
+def dome(f, h, max_steps=-1, out=None, allow_not_converged=False):
+    """Dome extraction (Eq. 7): f - HMAX_h(f)."""
+    return _operator("gc_dome", f, (float(h),), max_steps, out, allow_not_converged)
+
+
+def hfill(f, max_steps=-1, out=None, allow_not_converged=False):
+    """Hole filling (Eq. 8-9): reconstruction by erosion of the border
+    marker (f on the border, max f inside) above f."""
+    return _operator("gc_hfill", f, (), max_steps, out, allow_not_converged)
+
+
+def raobj(f, max_steps=-1, out=None, allow_not_converged=False):
+    """Removal of objects touching the border (Eq. 10-11)."""
+    return _operator("gc_raobj", f, (), max_steps, out, allow_not_converged)
+
+
+def open_by_reconstruction(f, size, max_steps=-1, out=None, allow_not_converged=False):
+    """Opening by reconstruction (Eq. 12): reconstruction by dilation of
+    size plain erosions of f, under f."""
+    return _operator("gc_open_by_reconstruction", f, (int(size),), max_steps, out,
+                     allow_not_converged)
+
+
 def set_tuning(block_steps: int = 0, tile: int = -1) -> None:
     """Override steps per launch and tile family (0 / -1: built-in choice)."""
     abi.check(abi.gc_set_tuning(int(block_steps), int(tile)), "gc_set_tuning")

@@ -90,3 +90,49 @@ def test_tuning_hook_validates():
     assert abi.gc_set_tuning(64, -1) == abi.GC_ERR_INVALID_ARG
     assert abi.gc_set_tuning(4, 9) == abi.GC_ERR_INVALID_ARG
     assert abi.gc_set_tuning(0, -1) == abi.GC_OK
+
+
+def _steps():
+    return ctypes.c_int64(123)
+
+
+@pytest.mark.parametrize("call", [
+    # h negative, NaN or infinite; u8 h not an integer
+    lambda s: abi.gc_hmax(abi.GC_F32, FAKE, FAKE + (1 << 20), shape(8, 8, 8), -1.0, -1, s, None),
+    lambda s: abi.gc_dome(abi.GC_F64, FAKE, FAKE + (1 << 20), shape(8, 8, 8), float("nan"), -1, s,
+                          None),
+    lambda s: abi.gc_hmax(abi.GC_F64, FAKE, FAKE + (1 << 20), shape(8, 8, 8), float("inf"), -1, s,
+                          None),
+    lambda s: abi.gc_hmax(abi.GC_U8, FAKE, FAKE + (1 << 20), shape(8, 8, 8), 2.5, -1, s, None),
+    # negative erosion size
+    lambda s: abi.gc_open_by_reconstruction(abi.GC_U8, FAKE, FAKE + (1 << 20), shape(8, 8, 8), -1,
+                                            -1, s, None),
+    # null pointers, pitch < width, unknown dtype
+    lambda s: abi.gc_hfill(abi.GC_U8, None, FAKE, shape(8, 8, 8), -1, s, None),
+    lambda s: abi.gc_raobj(abi.GC_U8, FAKE, None, shape(8, 8, 8), -1, s, None),
+    lambda s: abi.gc_raobj(abi.GC_F32, FAKE, FAKE + (1 << 20), shape(8, 8, 7), -1, s, None),
+    lambda s: abi.gc_hfill(5, FAKE, FAKE + (1 << 20), shape(8, 8, 8), -1, s, None),
+])
+def test_operator_invalid_arguments(call):
+    s = _steps()
+    assert call(ctypes.byref(s)) == abi.GC_ERR_INVALID_ARG
+    assert s.value == 0 or s.value == 123
+    assert abi.last_error() != ""
+
+
+def test_operator_aliasing_and_empty():
+    s = _steps()
+    sh = shape(100, 100, 128)
+    # out == f, and out overlapping f's last row: f is the reconstruction's mask
+    assert abi.gc_hfill(abi.GC_U8, FAKE, FAKE, sh, -1, ctypes.byref(s), None) == abi.GC_ERR_ALIAS
+    assert abi.gc_dome(abi.GC_F32, FAKE, FAKE + 4 * 99 * 128, sh, 1.0, -1, ctypes.byref(s),
+                       None) == abi.GC_ERR_ALIAS
+    # empty images: nothing to do, no device access
+    for fn in ("gc_hfill", "gc_raobj"):
+        s = _steps()
+        assert getattr(abi, fn)(abi.GC_F64, FAKE, FAKE, shape(0, 5, 1), -1, ctypes.byref(s),
+                                None) == abi.GC_OK
+        assert s.value == 0
+    assert abi.gc_hmax(abi.GC_U8, None, None, shape(7, 0, 7), 3.0, -1, None, None) == abi.GC_OK
+    assert abi.gc_open_by_reconstruction(abi.GC_U8, FAKE, FAKE, shape(0, 0, 0), 2, -1, None,
+                                         None) == abi.GC_OK

@@ -64,6 +64,13 @@ def headline_u8_erosion(size: int = 1024, seed: int = 2, h: int = 40):
     return sat_add(m, h), m
 
 
+def operator_u8(size: int = 1024, seed: int = 2, sigma: float = 8.0) -> np.ndarray:
+    """1024x1024 u8 input of the reconstruction-based operators: the same
+    blurred-noise image as the headline mask (the stand-in for the 1024x1024
+    8-bit test image of the paper's operator timings)."""
+    return blur(size, size, sigma, seed)
+
+
 def plain_input(dtype, size: int = 1024):
     """1024x1024 plain-chain input: u8 uniform 0..255 (seed 3), f32 / f64
     uniform [0, 1) (seeds 4 / 5)."""
