@@ -258,24 +258,27 @@ def main():
         px_d = Fd.numel() * 200
         ms_fb = timed(fwd_bwd, 3, 1)
         ms_fo = timed(fwd_only, 3, 1)
-        # The two gradient kernels are streaming (HBM-bound): per launch one
-        # step over the 16 images.  Algorithmic bytes per pixel-step, f32:
-        # codes = read state + mask, write state + code (13 B);
-        # backward = read gradient + code, write gradient, read+write the
-        # mask gradient (17 B).
+        # The two gradient kernels run up to 8 steps per launch on tiles held
+        # in LDS.  Algorithmic HBM bytes per pixel and launch of k steps, s =
+        # sizeof(float): codes = read state + mask, write state, write k codes
+        # (3s + k); backward = read gradient + k codes, write gradient,
+        # read + write the mask gradient (4s + k).
         _, codes = gc.geodesic_chain_fwd_codes("dilate", Fd, Md, 32)
         gm = torch.zeros_like(Md)
-        c_ms, c_n, _ = kernel_profile(lambda: gc.geodesic_chain_fwd_codes("dilate", Fd, Md, 32, codes=codes), 2)
-        b_ms, b_n, _ = kernel_profile(lambda: gc.geodesic_chain_bwd(codes, Gd, gm), 2)
+        c_ms, c_n, c_st = kernel_profile(lambda: gc.geodesic_chain_fwd_codes("dilate", Fd, Md, 32, codes=codes), 2)
+        b_ms, b_n, b_st = kernel_profile(lambda: gc.geodesic_chain_bwd(codes, Gd, gm), 2)
         npx = Fd.numel()
+        k_c, k_b = c_st / max(c_n, 1), b_st / max(b_n, 1)
         extra["fwd_bwd_16x1024_f32_200"] = {
             "gpx_steps_per_s": round(px_d / ms_fb / 1e6, 2), "ms": round(ms_fb, 3),
             "forward_only_gpx_steps_per_s": round(px_d / ms_fo / 1e6, 2),
             "vs_plain": round(px_d / ms_fb / 1e6 / value, 4), "checkpoint_every": 32,
-            "codes_kernel": {"bound": "hbm", "avg_launch_ms": round(c_ms, 4),
-                             "achieved_gb_s": round(13 * npx / (c_ms * 1e-3) / 1e9, 1), "peak_gb_s": 8000},
-            "bwd_kernel": {"bound": "hbm", "avg_launch_ms": round(b_ms, 4),
-                           "achieved_gb_s": round(17 * npx / (b_ms * 1e-3) / 1e9, 1), "peak_gb_s": 8000}}
+            "codes_kernel": {"avg_launch_ms": round(c_ms, 4), "steps_per_launch": round(k_c, 2),
+                             "gpx_steps_per_s": round(npx * k_c / (c_ms * 1e-3) / 1e9, 1),
+                             "hbm_gb_s": round((12 + k_c) * npx / (c_ms * 1e-3) / 1e9, 1), "peak_gb_s": 8000},
+            "bwd_kernel": {"avg_launch_ms": round(b_ms, 4), "steps_per_launch": round(k_b, 2),
+                           "gpx_steps_per_s": round(npx * k_b / (b_ms * 1e-3) / 1e9, 1),
+                           "hbm_gb_s": round((16 + k_b) * npx / (b_ms * 1e-3) / 1e9, 1), "peak_gb_s": 8000}}
         del codes, gm
         del Fd, Md, Gd
         for dt_name, dt in (("u8", np.uint8), ("f32", np.float32), ("f64", np.float64)):
