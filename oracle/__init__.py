@@ -262,3 +262,45 @@ def open_by_reconstruction(f, s, max_steps=-1):
     if s < 0:
         raise ValueError("s must be >= 0")
     return reconstruct(DILATE, chain(ERODE, f, int(s)), f, max_steps)
+
+
+def quasi_distance(f):
+    """Quasi-distance transform (Eq. 13-15, Algorithm 6).
+
+    Returns (d_l1, d, r, erosion_steps, eta_steps):
+      - plain erosions eps_j(f) = eps_1(eps_{j-1}(f)) (Eq. 4 without a mask)
+        are applied until one changes nothing, after which every residual is
+        0; erosion_steps counts the ones that changed a pixel;
+      - r = the largest residual eps_{j-1}(f) - eps_j(f) over j, in f's
+        dtype, and d (int32) = the first j that reaches it, 0 where every
+        residual is 0 (a later j replaces it only if its residual is
+        strictly larger);
+      - d_l1 (int32) = eta applied to d until it stops changing, with
+        eta(g)(p) = eps_1(g)(p) + 1 where g(p) - eps_1(g)(p) > 1, else g(p)
+        (Eq. 14-15); eta_steps counts the applications that changed a pixel.
+    """
+    f = _check_image(f)
+    r = np.zeros_like(f)
+    d = np.zeros(f.shape, dtype=np.int32)
+    cur = f
+    j = 0
+    while f.size:
+        nxt = step(ERODE, cur)
+        if np.array_equal(nxt, cur):
+            break
+        j += 1
+        res = _sub_in_dtype(cur, nxt)   # an erosion never raises a pixel
+        upd = res > r
+        r[upd] = res[upd]
+        d[upd] = j
+        cur = nxt
+    g = d.astype(np.float64)
+    eta = 0
+    while f.size:
+        e = step(ERODE, g)
+        new = np.where(g - e > 1, e + 1, g)
+        if np.array_equal(new, g):
+            break
+        eta += 1
+        g = new
+    return g.astype(np.int32), d, r, j, eta
