@@ -225,6 +225,15 @@ def main():
             chain_len = pre + got["steps"]
             ops_extra[name] = {"steps_changed": got["steps"], "chain_steps": chain_len, "ms": round(ms_o, 4),
                                "gpx_steps_per_s": round(px * chain_len / ms_o / 1e6, 2)}
+        got = {}
+
+        def run_qdt():
+            _, _, got["erode"], got["eta"] = gc.quasi_distance(fo, lipschitz=True)
+
+        ms_q = timed(run_qdt, max(3, args.steps // 4), 1)
+        q_len = got["erode"] + got["eta"]
+        ops_extra["qdt"] = {"erosion_steps": got["erode"], "eta_steps": got["eta"], "chain_steps": q_len,
+                            "ms": round(ms_q, 4), "gpx_steps_per_s": round(px * q_len / ms_q / 1e6, 2)}
         extra["operators_1024_u8"] = ops_extra
         del fo, oo
         # Batched: 64 uneven images in one persistent graph-recorded launch.

@@ -162,6 +162,33 @@ int gc_open_by_reconstruction(gc_dtype dtype, const void *f, void *out, gc_shape
                               void *hip_stream);
 
 /* ---------------------------------------------------------------------
+ * Quasi-distance transform (Section 2, Eq. 13-15; Algorithm 6).
+ *
+ * Applies plain 3x3 erosions eps_j = eps_1(eps_{j-1}(f)) until one changes
+ * no pixel (at most max(X, Y) - 1 of them change anything).  For every
+ * pixel, residual = the largest eps_{j-1}(f) - eps_j(f) over j (in f's
+ * dtype) and d = the first j reaching it (0 where every residual is 0); a
+ * later erosion replaces them only with a strictly larger residual.  With
+ * lipschitz != 0, eta(g) = min(g, eps_1(g) + 1) is then applied to d until
+ * it changes nothing (Eq. 14-15: where g exceeds its window minimum by more
+ * than 1 it drops to that minimum + 1), giving the 1-Lipschitz d_L1.
+ *
+ *   f         input image (device, read-only).
+ *   dist      int32 output, d_L1 (lipschitz != 0) or d (device, 4-byte
+ *             aligned); element (x, y) at y * pitch + x, the same pitch in
+ *             elements as f.
+ *   residual  optional output of f's dtype, same pitch (NULL: not stored).
+ *   *erosion_steps, *eta_steps (host, may be NULL): the erosions and eta
+ *             applications that changed at least one pixel.
+ *
+ * dist and residual must not overlap f or each other (GC_ERR_ALIAS).  The
+ * call SYNCHRONISES hip_stream (the chain lengths are data-dependent).
+ * ------------------------------------------------------------------- */
+int gc_quasi_distance(gc_dtype dtype, const void *f, int32_t *dist, void *residual,
+                      gc_shape shape, int32_t lipschitz, int64_t *erosion_steps,
+                      int64_t *eta_steps, void *hip_stream);
+
+/* ---------------------------------------------------------------------
  * Batches: many independent chains (Eq. 4), each with its own image size
  * and number of steps, run by ONE persistent kernel launch recorded in a
  * HIP graph.  There is no batching in the paper; its closest analogue is

@@ -21,6 +21,7 @@ from .ops import (  # noqa: F401
     hfill,
     hmax,
     open_by_reconstruction,
+    quasi_distance,
     raobj,
     reconstruct_by_dilation,
     reconstruct_by_erosion,

@@ -22,6 +22,7 @@
 #include "persistent.hpp"
 #include "grad_block.hpp"
 #include "operators.hpp"
+#include "qdt_block.hpp"
 
 namespace geochain {
 
@@ -647,6 +648,132 @@ static int run_operator_t(gc_dtype dtype, int which, const T *f, T *out, const g
         GC_HIP(hipGetLastError());
     }
     return rrc;
+}
+
+// ---------------------------------------------------------------------------
+// quasi-distance transform (Eq. 13-15)
+// ---------------------------------------------------------------------------
+template <typename T, int PHASE, int CW, int RPW, int NW>
+static void launch_qdt(const QdtArgs &qa, int grid, hipStream_t st) {
+    hipLaunchKernelGGL((qdt_block_kernel<T, PHASE, CW, RPW, NW>), dim3(grid), dim3(64 * NW), 0, st, qa);
+}
+
+struct QdtLayout {
+    int rx, ry, k;  // region columns, rows; steps per launch
+    void (*launch)(const QdtArgs &, int, hipStream_t);
+};
+
+// 128 x 128 regions (two columns per lane), k = 32; f64 keeps one column
+// per lane (64 x 128, k = 16) so its residuals fit in registers.
+template <typename T, int PHASE>
+static QdtLayout qdt_layout() {
+    if constexpr (sizeof(T) == 8) return {64, 128, 16, launch_qdt<T, PHASE, 1, 8, 16>};
+    else return {128, 128, 32, launch_qdt<T, PHASE, 2, 8, 16>};
+}
+
+// Runs one phase, k steps per launch, until a step changes nothing.  The
+// state starts in src0 and alternates between buf0 and buf1; *result is the
+// buffer holding the final state and *changed the number of steps that
+// changed a pixel.
+static int run_qdt_phase(const QdtLayout &L, const gc_shape &s, const void *src0, void *buf0, void *buf1,
+                         void *res, int32_t *dist, Workspace *ws, hipStream_t st, int64_t *changed,
+                         const void **result) {
+    constexpr int MAX_GROUP = 64;
+    const int k = L.k;
+    const int core_x = L.rx - 2 * k, core_y = L.ry - 2 * k;
+    const int tiles_x = (int)((s.width + core_x - 1) / core_x);
+    const int tiles = tiles_x * (int)((s.height + core_y - 1) / core_y);
+    // Both chains stop changing within max(X, Y) - 1 steps; the bound only
+    // guards the loop.
+    const int64_t bound = 2 * std::max(s.width, s.height) + 2 * (int64_t)k * MAX_GROUP;
+    const uint32_t full = (uint32_t)((1ull << k) - 1);
+    int64_t total = 0, launched = 0;
+    const void *cur = src0;
+    *result = src0;
+    int group = 8;
+    for (bool done = false; !done;) {
+        if (launched * k > bound) return fail(GC_ERR_HIP, "quasi-distance chain did not settle");
+        hipLaunchKernelGGL(fill_words_kernel, dim3(1), dim3(128), 0, st, ws->words, group, 0u);
+        GC_HIP(hipGetLastError());
+        std::vector<const void *> dsts(group);
+        for (int j = 0; j < group; ++j) {
+            void *dst = (launched % 2 == 0) ? buf0 : buf1;
+            QdtArgs qa{};
+            qa.b.src = cur;
+            qa.b.dst = dst;
+            qa.b.width = (int32_t)s.width;
+            qa.b.height = (int32_t)s.height;
+            qa.b.pitch = s.pitch;
+            qa.b.k = k;
+            qa.b.halo = k;
+            qa.b.core_x = core_x;
+            qa.b.core_y = core_y;
+            qa.b.tiles_x = tiles_x;
+            qa.b.change_word = ws->words + j;
+            qa.b.prev_word = j > 0 ? ws->words + (j - 1) : nullptr;
+            qa.b.prev_full = full;
+            qa.res = res;
+            qa.dist = dist;
+            qa.step0 = (int32_t)(launched * k);
+            const int pr = prof_begin(st, k);
+            L.launch(qa, tiles, st);
+            prof_end(pr, st);
+            GC_HIP(hipGetLastError());
+            dsts[j] = dst;
+            cur = dst;
+            ++launched;
+        }
+        GC_HIP(hipMemcpyAsync(ws->host_words, ws->words, group * 4, hipMemcpyDeviceToHost, st));
+        GC_HIP(hipStreamSynchronize(st));
+        for (int j = 0; j < group; ++j) {
+            const uint32_t wrd = ws->host_words[j];
+            *result = dsts[j];
+            if (wrd == full) {
+                total += k;
+                continue;
+            }
+            total += __builtin_popcount(wrd);
+            done = true;
+            break;
+        }
+        group = std::min(group * 2, MAX_GROUP);
+    }
+    *changed = total;
+    return GC_OK;
+}
+
+template <typename T>
+static int run_qdt_t(const T *f, int32_t *dist, T *residual, const gc_shape &s, bool lipschitz,
+                     int64_t *erosion_steps, int64_t *eta_steps, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const size_t npx = (size_t)((s.height - 1) * s.pitch + s.width);
+    const size_t ext_t = (npx * sizeof(T) + 255) & ~(size_t)255;
+    const size_t ext_i = (npx * 4 + 255) & ~(size_t)255;
+    Workspace *ws = nullptr;
+    int rc = get_workspace(stream, std::max(3 * ext_t, ext_i), 65, &ws);
+    if (rc != GC_OK) return rc;
+    char *base = static_cast<char *>(ws->buf);
+    T *res = residual ? residual : reinterpret_cast<T *>(base + 2 * ext_t);
+
+    const void *state = nullptr;
+    int64_t n_erode = 0;
+    rc = run_qdt_phase(qdt_layout<T, QDT_ERODE>(), s, f, base, base + ext_t, res, dist, ws, st, &n_erode,
+                       &state);
+    if (rc != GC_OK) return rc;
+    if (erosion_steps) *erosion_steps = n_erode;
+    int64_t n_eta = 0;
+    if (lipschitz) {
+        const void *out = nullptr;
+        rc = run_qdt_phase(qdt_layout<uint32_t, QDT_ETA>(), s, dist, base, dist, nullptr, nullptr, ws, st,
+                           &n_eta, &out);
+        if (rc != GC_OK) return rc;
+        if (out != (const void *)dist) {
+            rc = copy_image(dist, out, s, 4, st);
+            if (rc != GC_OK) return rc;
+        }
+    }
+    if (eta_steps) *eta_steps = n_eta;
+    return GC_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1360,6 +1487,38 @@ int gc_open_by_reconstruction(gc_dtype dtype, const void *f, void *out, gc_shape
                               int64_t max_steps, int64_t *steps_out, void *hip_stream) {
     return geodesic_operator(dtype, GOP_OPEN_REC, f, out, shape, 0.0, size, max_steps, steps_out,
                              hip_stream);
+}
+
+int gc_quasi_distance(gc_dtype dtype, const void *f, int32_t *dist, void *residual, gc_shape shape,
+                      int32_t lipschitz, int64_t *erosion_steps, int64_t *eta_steps, void *hip_stream) {
+    g_last_error.clear();
+    if (erosion_steps) *erosion_steps = 0;
+    if (eta_steps) *eta_steps = 0;
+    int rc = validate_shape(dtype, shape);
+    if (rc != GC_OK) return rc;
+    if (shape.width == 0 || shape.height == 0) return GC_OK;
+    if (!f || !dist) return fail(GC_ERR_INVALID_ARG, "null image pointer");
+    if ((uintptr_t)dist % 4) return fail(GC_ERR_INVALID_ARG, "dist must be 4-byte aligned");
+    const size_t es = elem_size(dtype);
+    const auto ef = extent(f, shape, es);
+    const auto ed = extent(dist, shape, 4);
+    if (overlap(ef, ed)) return fail(GC_ERR_ALIAS, "dist overlaps f");
+    if (residual) {
+        const auto er = extent(residual, shape, es);
+        if (overlap(er, ef) || overlap(er, ed)) return fail(GC_ERR_ALIAS, "residual overlaps f or dist");
+    }
+    switch (dtype) {
+        case GC_U8:
+            return run_qdt_t<uint8_t>((const uint8_t *)f, dist, (uint8_t *)residual, shape, lipschitz != 0,
+                                      erosion_steps, eta_steps, hip_stream);
+        case GC_F32:
+            return run_qdt_t<float>((const float *)f, dist, (float *)residual, shape, lipschitz != 0,
+                                    erosion_steps, eta_steps, hip_stream);
+        case GC_F64:
+            return run_qdt_t<double>((const double *)f, dist, (double *)residual, shape, lipschitz != 0,
+                                     erosion_steps, eta_steps, hip_stream);
+    }
+    return fail(GC_ERR_INVALID_ARG, "unknown dtype");
 }
 
 int gc_geodesic_chain_fwd_codes(gc_dtype dtype, gc_op op, const void *marker, const void *mask, void *out,

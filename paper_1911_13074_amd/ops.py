@@ -178,6 +178,24 @@ def open_by_reconstruction(f, size, max_steps=-1, out=None, allow_not_converged=
                      allow_not_converged)
 
 
+def quasi_distance(f, lipschitz=True, with_residual=False):
+    """Quasi-distance transform (Eq. 13-15).  Returns (dist, residual,
+    erosion_steps, eta_steps): dist is int32 (d_L1 if lipschitz, else the
+    discontinuous d of Eq. 13), residual is None unless requested.
+    Synchronises the current stream."""
+    _check_image(f, "f")
+    dist = torch.empty_strided(f.shape, f.stride(), dtype=torch.int32, device=f.device)
+    res = torch.empty_strided(f.shape, f.stride(), dtype=f.dtype, device=f.device) if with_residual else None
+    n_erode = ctypes.c_int64(0)
+    n_eta = ctypes.c_int64(0)
+    with torch.cuda.device(f.device):
+        st = abi.gc_quasi_distance(_dtype_code(f), _ptr(f), _ptr(dist), _ptr(res) if res is not None else None,
+                                   _shape(f), 1 if lipschitz else 0, ctypes.byref(n_erode),
+                                   ctypes.byref(n_eta), _stream(f))
+    abi.check(st, "gc_quasi_distance")
+    return dist, res, int(n_erode.value), int(n_eta.value)
+
+
 def set_tuning(block_steps: int = 0, tile: int = -1) -> None:
     """Override steps per launch and tile family (0 / -1: built-in choice)."""
     abi.check(abi.gc_set_tuning(int(block_steps), int(tile)), "gc_set_tuning")

@@ -136,3 +136,20 @@ def test_operator_aliasing_and_empty():
     assert abi.gc_hmax(abi.GC_U8, None, None, shape(7, 0, 7), 3.0, -1, None, None) == abi.GC_OK
     assert abi.gc_open_by_reconstruction(abi.GC_U8, FAKE, FAKE, shape(0, 0, 0), 2, -1, None,
                                          None) == abi.GC_OK
+
+
+def test_quasi_distance_validation():
+    sh = shape(64, 32, 64)
+    n1, n2 = ctypes.c_int64(5), ctypes.c_int64(5)
+    q = abi.gc_quasi_distance
+    assert q(abi.GC_U8, None, FAKE, None, sh, 1, ctypes.byref(n1), ctypes.byref(n2), None) == abi.GC_ERR_INVALID_ARG
+    assert n1.value == 0 and n2.value == 0
+    assert q(abi.GC_U8, FAKE, None, None, sh, 1, None, None, None) == abi.GC_ERR_INVALID_ARG
+    assert q(abi.GC_F32, FAKE, FAKE + (1 << 20) + 2, None, sh, 1, None, None, None) == abi.GC_ERR_INVALID_ARG
+    assert q(abi.GC_F32, FAKE, FAKE, None, sh, 1, None, None, None) == abi.GC_ERR_ALIAS
+    # dist overlapping the last row of f (f32: 4 bytes per element)
+    assert q(abi.GC_F32, FAKE, FAKE + 4 * 31 * 64, None, sh, 0, None, None, None) == abi.GC_ERR_ALIAS
+    assert q(abi.GC_U8, FAKE, FAKE + (1 << 20), FAKE + (1 << 20) + 8, sh, 1, None, None,
+             None) == abi.GC_ERR_ALIAS
+    assert q(9, FAKE, FAKE + (1 << 20), None, sh, 1, None, None, None) == abi.GC_ERR_INVALID_ARG
+    assert q(abi.GC_U8, None, None, None, shape(0, 3, 0), 1, ctypes.byref(n1), None, None) == abi.GC_OK
