@@ -304,3 +304,38 @@ def quasi_distance(f):
         eta += 1
         g = new
     return g.astype(np.int32), d, r, j, eta
+
+
+def opening(f, s):
+    """gamma_s(f) = delta_s(eps_s(f)): s plain erosions, then s plain
+    dilations (Eq. 16)."""
+    return chain(DILATE, chain(ERODE, f, int(s)), int(s))
+
+
+def closing(f, s):
+    """phi_s(f) = eps_s(delta_s(f)) (Eq. 19)."""
+    return chain(ERODE, chain(DILATE, f, int(s)), int(s))
+
+
+def granulometry(f, s_max):
+    """Granulometric function G_s(f) = sum over P of gamma_s(f), s = 0..s_max
+    (Eq. 17; gamma_0 = f), each sum exactly rounded to float64 (math.fsum),
+    and the pattern spectrum PS_s = G_s - G_{s+1}, s = 0..s_max-1 (Eq. 18)."""
+    import math
+    f = _check_image(f)
+    if s_max < 0:
+        raise ValueError("s_max must be >= 0")
+    G = np.array([math.fsum(opening(f, s).astype(np.float64).ravel()) for s in range(int(s_max) + 1)])
+    return G, G[:-1] - G[1:]
+
+
+def asf(f, s_max):
+    """Alternating sequential filter starting with an opening (Eq. 20):
+    phi_s(gamma_s(... phi_1(gamma_1(f)))) up to s = s_max; s_max = 0 is f."""
+    f = _check_image(f)
+    if s_max < 0:
+        raise ValueError("s_max must be >= 0")
+    g = f.copy()
+    for s in range(1, int(s_max) + 1):
+        g = closing(opening(g, s), s)
+    return g
