@@ -234,6 +234,13 @@ def main():
         q_len = got["erode"] + got["eta"]
         ops_extra["qdt"] = {"erosion_steps": got["erode"], "eta_steps": got["eta"], "chain_steps": q_len,
                             "ms": round(ms_q, 4), "gpx_steps_per_s": round(px * q_len / ms_q / 1e6, 2)}
+        # pattern spectrum PS_[0,11] and ASF_11 (Table 5): 11 + 66 and 264 steps
+        ms_g = timed(lambda: gc.granulometry(fo, 11), max(3, args.steps // 4), 1)
+        ops_extra["pattern_spectrum_0_11"] = {"chain_steps": 77, "ms": round(ms_g, 4),
+                                              "gpx_steps_per_s": round(px * 77 / ms_g / 1e6, 2)}
+        ms_a = timed(lambda: gc.asf(fo, 11, out=oo), max(3, args.steps // 4), 1)
+        ops_extra["asf_11"] = {"chain_steps": 264, "ms": round(ms_a, 4),
+                               "gpx_steps_per_s": round(px * 264 / ms_a / 1e6, 2)}
         extra["operators_1024_u8"] = ops_extra
         del fo, oo
         # Batched: 64 uneven images in one persistent graph-recorded launch.

@@ -162,6 +162,27 @@ int gc_open_by_reconstruction(gc_dtype dtype, const void *f, void *out, gc_shape
                               void *hip_stream);
 
 /* ---------------------------------------------------------------------
+ * Granulometry and alternating sequential filters (Section 2, Eq. 16-20).
+ *
+ * gamma_s(f) = delta_s(eps_s(f)) is the opening of size s (s plain 3x3
+ * erosions, then s plain 3x3 dilations), phi_s(f) = eps_s(delta_s(f)) the
+ * closing.
+ *
+ * gc_granulometry: G[s] = sum over all pixels of gamma_s(f), for
+ *   s = 0..s_max (gamma_0 = f), and PS[s] = G[s] - G[s+1] for
+ *   s = 0..s_max-1 (the pattern spectrum).  G (s_max + 1 values) and PS
+ *   (s_max values, may be NULL) are HOST arrays of double; the sums are
+ *   accumulated in double in a fixed order (exact for u8 images), so repeated
+ *   calls return identical values.  SYNCHRONISES hip_stream.
+ * gc_asf: out = phi_smax(gamma_smax(... phi_1(gamma_1(f)))); s_max = 0
+ *   copies f.  out may equal f; out must not partially overlap f.
+ * ------------------------------------------------------------------- */
+int gc_granulometry(gc_dtype dtype, const void *f, gc_shape shape, int32_t s_max,
+                    double *G, double *PS, void *hip_stream);
+int gc_asf(gc_dtype dtype, const void *f, void *out, gc_shape shape, int32_t s_max,
+           void *hip_stream);
+
+/* ---------------------------------------------------------------------
  * Quasi-distance transform (Section 2, Eq. 13-15; Algorithm 6).
  *
  * Applies plain 3x3 erosions eps_j = eps_1(eps_{j-1}(f)) until one changes

@@ -9,6 +9,7 @@ from .abi import GeochainError  # noqa: F401
 from .autograd import GeodesicChainFunction, geodesic_chain  # noqa: F401
 from .ops import (  # noqa: F401
     BatchPlan,
+    asf,
     autotune,
     autotune_clear,
     dilate_chain,
@@ -18,6 +19,7 @@ from .ops import (  # noqa: F401
     geodesic_chain_fwd_codes,
     geodesic_dilate_chain,
     geodesic_erode_chain,
+    granulometry,
     hfill,
     hmax,
     open_by_reconstruction,

@@ -60,6 +60,9 @@ SIGNATURES = {
     "gc_raobj": (ctypes.c_int, [_DT, _VP, _VP, gc_shape, _I64, _P_I64, _VP]),
     "gc_open_by_reconstruction": (ctypes.c_int, [_DT, _VP, _VP, gc_shape, _I64, _I64, _P_I64, _VP]),
     "gc_quasi_distance": (ctypes.c_int, [_DT, _VP, _VP, _VP, gc_shape, _I32, _P_I64, _P_I64, _VP]),
+    "gc_granulometry": (ctypes.c_int, [_DT, _VP, gc_shape, _I32, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double), _VP]),
+    "gc_asf": (ctypes.c_int, [_DT, _VP, _VP, gc_shape, _I32, _VP]),
     "gc_set_tuning": (ctypes.c_int, [_I32, _I32]),
     "gc_plan_create": (ctypes.c_int, [_DT, _DT, ctypes.POINTER(gc_item), _I32,
                                       ctypes.POINTER(ctypes.c_void_p)]),

@@ -189,6 +189,8 @@ struct Workspace {
     uint32_t *host_words = nullptr; // pinned mirror
     size_t nwords = 0;
     void *partials = nullptr;       // PARTIALS_MAX per-workgroup extrema (operators)
+    void *buf2 = nullptr;           // images of composed operators (granulometry)
+    size_t bytes2 = 0;
 };
 
 static std::mutex g_ws_mu;
@@ -249,6 +251,30 @@ static int get_partials(void *stream, void **out) {
         }
     }
     *out = w.partials;
+    return GC_OK;
+}
+
+// Per-(device, stream) second buffer for operators composed of several
+// chains (run_chain keeps the first one for its ping-pong).
+static int get_buf2(void *stream, size_t bytes, void **out) {
+    int dev = 0;
+    GC_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(g_ws_mu);
+    Workspace &w = g_ws[{dev, stream}];
+    if (w.bytes2 < bytes) {
+        if (w.buf2) {
+            GC_HIP(hipStreamSynchronize((hipStream_t)stream));
+            GC_HIP(hipFree(w.buf2));
+            w.buf2 = nullptr;
+            w.bytes2 = 0;
+        }
+        if (hipMalloc(&w.buf2, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(GC_ERR_NO_MEMORY, "operator workspace of %zu bytes", bytes);
+        }
+        w.bytes2 = bytes;
+    }
+    *out = w.buf2;
     return GC_OK;
 }
 
@@ -648,6 +674,86 @@ static int run_operator_t(gc_dtype dtype, int which, const T *f, T *out, const g
         GC_HIP(hipGetLastError());
     }
     return rrc;
+}
+
+// ---------------------------------------------------------------------------
+// granulometry and alternating sequential filters (Eq. 16-20)
+// ---------------------------------------------------------------------------
+// G[s] = sum of gamma_s(f), s = 0..s_max.  The erosions are kept incremental
+// (eps_s = eps_1(eps_{s-1}), the s-fold composition of Eq. 16), the
+// dilations of each opening start from eps_s.
+template <typename T>
+static int run_granulometry_t(gc_dtype dtype, const T *f, const gc_shape &s, int s_max, double *G,
+                              void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const size_t npx = (size_t)((s.height - 1) * s.pitch + s.width);
+    const size_t ext = (npx * sizeof(T) + 255) & ~(size_t)255;
+    void *b2 = nullptr;
+    int rc = get_buf2(stream, 3 * ext + (size_t)(s_max + 1) * sizeof(double), &b2);
+    if (rc != GC_OK) return rc;
+    void *partials = nullptr;
+    rc = get_partials(stream, &partials);
+    if (rc != GC_OK) return rc;
+    char *base = static_cast<char *>(b2);
+    T *opened = reinterpret_cast<T *>(base);
+    T *eroded[2] = {reinterpret_cast<T *>(base + ext), reinterpret_cast<T *>(base + 2 * ext)};
+    double *sums = reinterpret_cast<double *>(base + 3 * ext);
+    const T *eps = f;
+    for (int sz = 0; sz <= s_max; ++sz) {
+        const T *img = f;
+        if (sz > 0) {
+            T *next = eroded[sz % 2];
+            rc = run_chain(dtype, OP_ERODE, MODE_PLAIN, eps, nullptr, next, s, 1, stream);
+            if (rc != GC_OK) return rc;
+            eps = next;
+            rc = run_chain(dtype, OP_DILATE, MODE_PLAIN, eps, nullptr, opened, s, sz, stream);
+            if (rc != GC_OK) return rc;
+            img = opened;
+        }
+        const bool vec = rows_aligned16(s, sizeof(T), img, img);
+        const PixelArgs<T> p = pixel_args<T>(s, img, nullptr, nullptr, vec);
+        const int grid = px_grid(p.n_chunks, PARTIALS_MAX);
+        if (vec)
+            hipLaunchKernelGGL((sum_kernel<T, true>), dim3(grid), dim3(PX_THREADS), 0, st, p, (double *)partials);
+        else
+            hipLaunchKernelGGL((sum_kernel<T, false>), dim3(grid), dim3(PX_THREADS), 0, st, p, (double *)partials);
+        hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(PX_THREADS), 0, st, (const double *)partials, grid,
+                           sums + sz);
+        GC_HIP(hipGetLastError());
+    }
+    std::vector<double> host(s_max + 1);
+    GC_HIP(hipMemcpyAsync(host.data(), sums, (s_max + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+    GC_HIP(hipStreamSynchronize(st));
+    std::copy(host.begin(), host.end(), G);
+    return GC_OK;
+}
+
+// phi_s(gamma_s(...)) as one list of plain chains; consecutive chains of the
+// same direction are one chain of the summed length (delta_a of delta_b is
+// delta_{a+b} by Eq. 4), so the sequence runs as E1 D2 E3 D4 ... D2S ES.
+static int run_asf(gc_dtype dtype, const void *f, void *out, const gc_shape &s, int s_max, void *stream) {
+    const size_t es = elem_size(dtype);
+    if (s_max == 0) return copy_image(out, f, s, es, (hipStream_t)stream);
+    std::vector<std::pair<int, int64_t>> seq;
+    auto push = [&](int op, int64_t n) {
+        if (!seq.empty() && seq.back().first == op)
+            seq.back().second += n;
+        else
+            seq.push_back({op, n});
+    };
+    for (int sz = 1; sz <= s_max; ++sz) {
+        push(OP_ERODE, sz);   // gamma_s: erosions, then dilations
+        push(OP_DILATE, sz);
+        push(OP_DILATE, sz);  // phi_s: dilations, then erosions
+        push(OP_ERODE, sz);
+    }
+    const void *cur = f;
+    for (const auto &c : seq) {
+        const int rc = run_chain(dtype, c.first, MODE_PLAIN, cur, nullptr, out, s, c.second, stream);
+        if (rc != GC_OK) return rc;
+        cur = out;
+    }
+    return GC_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1487,6 +1593,38 @@ int gc_open_by_reconstruction(gc_dtype dtype, const void *f, void *out, gc_shape
                               int64_t max_steps, int64_t *steps_out, void *hip_stream) {
     return geodesic_operator(dtype, GOP_OPEN_REC, f, out, shape, 0.0, size, max_steps, steps_out,
                              hip_stream);
+}
+
+int gc_granulometry(gc_dtype dtype, const void *f, gc_shape shape, int32_t s_max, double *G, double *PS,
+                    void *hip_stream) {
+    g_last_error.clear();
+    int rc = validate_shape(dtype, shape);
+    if (rc != GC_OK) return rc;
+    if (s_max < 0) return fail(GC_ERR_INVALID_ARG, "s_max < 0");
+    if (!G) return fail(GC_ERR_INVALID_ARG, "null G");
+    if (shape.width == 0 || shape.height == 0) {
+        std::fill(G, G + s_max + 1, 0.0);
+    } else {
+        if (!f) return fail(GC_ERR_INVALID_ARG, "null image pointer");
+        switch (dtype) {
+            case GC_U8: rc = run_granulometry_t<uint8_t>(dtype, (const uint8_t *)f, shape, s_max, G, hip_stream); break;
+            case GC_F32: rc = run_granulometry_t<float>(dtype, (const float *)f, shape, s_max, G, hip_stream); break;
+            case GC_F64: rc = run_granulometry_t<double>(dtype, (const double *)f, shape, s_max, G, hip_stream); break;
+        }
+        if (rc != GC_OK) return rc;
+    }
+    if (PS)
+        for (int i = 0; i < s_max; ++i) PS[i] = G[i] - G[i + 1];
+    return GC_OK;
+}
+
+int gc_asf(gc_dtype dtype, const void *f, void *out, gc_shape shape, int32_t s_max, void *hip_stream) {
+    g_last_error.clear();
+    int rc = validate_images(dtype, f, nullptr, out, shape);
+    if (rc != GC_OK) return rc;
+    if (s_max < 0) return fail(GC_ERR_INVALID_ARG, "s_max < 0");
+    if (shape.width == 0 || shape.height == 0) return GC_OK;
+    return run_asf(dtype, f, out, shape, s_max, hip_stream);
 }
 
 int gc_quasi_distance(gc_dtype dtype, const void *f, int32_t *dist, void *residual, gc_shape shape,

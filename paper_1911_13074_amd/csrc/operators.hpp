@@ -7,6 +7,7 @@
 //   hole filling, Eq. 8-9    marker: f on the border B, max f inside
 //                                  (extremum_kernel, then PX_BORDER)
 //   border objects, Eq. 10-11  marker: f on B, min f inside; then f - rec
+//   granulometry, Eq. 17       sum of an opened image (sum_kernel)
 //
 // Arithmetic is done in the image's dtype: uint8 differences saturate at 0,
 // float differences are one IEEE subtraction.  The border B is the first and
@@ -155,6 +156,53 @@ __global__ __launch_bounds__(PX_THREADS) void pixel_kernel(PixelArgs<T> p) {
             }
         }
     });
+}
+
+// ---------------------------------------------------------------------------
+// Sum of an image (granulometric function, Eq. 17) in float64, in a fixed
+// order: each thread adds its chunks in turn, each workgroup reduces by a
+// fixed tree into one partial, and sum_partials_kernel adds those
+// partials in a fixed tree as well, so repeated calls give identical bits.
+// Integer-valued images sum exactly (below 2^53).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double red[PX_THREADS];
+    red[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = PX_THREADS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+template <typename T, bool VEC>
+__global__ __launch_bounds__(PX_THREADS) void sum_kernel(PixelArgs<T> p, double *partials) {
+    constexpr int V = VEC ? 16 / (int)sizeof(T) : 1;
+    double acc = 0.0;
+    for_chunks<VEC>(p, [&](int64_t, int64_t, int64_t off, int nvalid) {
+        if (VEC && nvalid == V) {
+            Chunk<T, V> c;
+            c.v = *reinterpret_cast<const uint4 *>(p.a + off);
+#pragma unroll
+            for (int j = 0; j < V; ++j) acc += (double)c.e[j];
+        } else {
+            for (int j = 0; j < nvalid; ++j) acc += (double)p.a[off + j];
+        }
+    });
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+// One workgroup: out[0] = sum of partials[0 .. n).
+__global__ __launch_bounds__(PX_THREADS) void sum_partials_kernel(const double *partials, int n, double *out) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += PX_THREADS) acc += partials[i];
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) out[0] = acc;
 }
 
 }  // namespace geochain

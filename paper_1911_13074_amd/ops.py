@@ -196,6 +196,31 @@ def quasi_distance(f, lipschitz=True, with_residual=False):
     return dist, res, int(n_erode.value), int(n_eta.value)
 
 
+def granulometry(f, s_max):
+    """Granulometric function G_s (s = 0..s_max) and pattern spectrum PS_s
+    (s = 0..s_max-1) of f (Eq. 16-18), as lists of floats.  Synchronises
+    the current stream."""
+    _check_image(f, "f")
+    s_max = int(s_max)
+    G = (ctypes.c_double * (s_max + 1))()
+    PS = (ctypes.c_double * max(s_max, 1))()
+    with torch.cuda.device(f.device):
+        st = abi.gc_granulometry(_dtype_code(f), _ptr(f), _shape(f), s_max, G, PS, _stream(f))
+    abi.check(st, "gc_granulometry")
+    return list(G), list(PS)[:s_max]
+
+
+def asf(f, s_max, out=None):
+    """Alternating sequential filter phi_s(gamma_s(... phi_1(gamma_1(f))))
+    up to s = s_max (Eq. 19-20)."""
+    _check_image(f, "f")
+    out = _out_like(f, out)
+    with torch.cuda.device(f.device):
+        st = abi.gc_asf(_dtype_code(f), _ptr(f), _ptr(out), _shape(f), int(s_max), _stream(f))
+    abi.check(st, "gc_asf")
+    return out
+
+
 def set_tuning(block_steps: int = 0, tile: int = -1) -> None:
     """Override steps per launch and tile family (0 / -1: built-in choice)."""
     abi.check(abi.gc_set_tuning(int(block_steps), int(tile)), "gc_set_tuning")

@@ -153,3 +153,17 @@ def test_quasi_distance_validation():
              None) == abi.GC_ERR_ALIAS
     assert q(9, FAKE, FAKE + (1 << 20), None, sh, 1, None, None, None) == abi.GC_ERR_INVALID_ARG
     assert q(abi.GC_U8, None, None, None, shape(0, 3, 0), 1, ctypes.byref(n1), None, None) == abi.GC_OK
+
+
+def test_granulometry_and_asf_validation():
+    G = (ctypes.c_double * 4)(7, 7, 7, 7)
+    sh = shape(16, 16, 16)
+    assert abi.gc_granulometry(abi.GC_U8, FAKE, sh, -1, G, None, None) == abi.GC_ERR_INVALID_ARG
+    assert abi.gc_granulometry(abi.GC_U8, FAKE, sh, 2, None, None, None) == abi.GC_ERR_INVALID_ARG
+    assert abi.gc_granulometry(abi.GC_U8, None, sh, 2, G, None, None) == abi.GC_ERR_INVALID_ARG
+    PS = (ctypes.c_double * 3)(7, 7, 7)
+    assert abi.gc_granulometry(abi.GC_F32, FAKE, shape(0, 4, 0), 3, G, PS, None) == abi.GC_OK
+    assert list(G) == [0, 0, 0, 0] and list(PS) == [0, 0, 0]
+    assert abi.gc_asf(abi.GC_U8, FAKE, FAKE + 1, sh, 1, None) == abi.GC_ERR_ALIAS
+    assert abi.gc_asf(abi.GC_U8, FAKE, FAKE + (1 << 20), sh, -2, None) == abi.GC_ERR_INVALID_ARG
+    assert abi.gc_asf(abi.GC_U8, None, None, shape(0, 0, 0), 2, None) == abi.GC_OK

@@ -1,0 +1,85 @@
+"""GPU parity of the granulometry, pattern spectrum and ASF (Eq. 16-20)
+through the C ABI against the oracle.  The ASF only selects values, so it is
+bit-exact.  G_s sums in float64 on both sides but in different orders: for
+u8 images every partial sum is an integer below 2^53, so G and PS are
+exact; for float images they agree within the bound of recursive float64
+summation, n * 2^-53 * sum|f| (n = pixel count), stated per test below."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+import paper_1911_13074_amd as gc
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [np.uint8, np.float32, np.float64]
+SHAPES = [(1, 1), (1, 300), (300, 1), (67, 129), (200, 517), (513, 385)]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def image(shape, dtype, seed):
+    f = workloads.blur(shape[0], shape[1], 2.0, seed) if min(shape) > 1 else \
+        np.random.default_rng(seed).integers(0, 256, size=shape).astype(np.uint8)
+    return f if dtype == np.uint8 else (f / 255.0 * 2.0 - 0.5).astype(dtype)
+
+
+def check_granulometry(f, s_max, what):
+    G, PS = gc.granulometry(dev(f), s_max)
+    rG, rPS = oracle.granulometry(f, s_max)
+    if f.dtype == np.uint8:
+        assert G == list(rG), what
+        assert PS == list(rPS), what
+    else:
+        tol = f.size * 2.0 ** -53 * float(np.abs(f.astype(np.float64)).sum())
+        np.testing.assert_allclose(G, rG, rtol=0, atol=tol, err_msg=what)
+        np.testing.assert_allclose(PS, rPS, rtol=0, atol=2 * tol, err_msg=what)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("shape", SHAPES)
+def test_granulometry_parity(dtype, shape):
+    check_granulometry(image(shape, dtype, seed=shape[0] + 3 * shape[1]), 6, f"{shape}")
+
+
+@pytest.mark.parametrize("s_max", [0, 1, 40])
+def test_granulometry_sizes(s_max):
+    check_granulometry(image((90, 130), np.uint8, seed=s_max), s_max, f"s_max={s_max}")
+
+
+def test_granulometry_is_deterministic():
+    F = dev(image((300, 411), np.float32, seed=2))
+    a = gc.granulometry(F, 5)
+    for _ in range(3):
+        assert gc.granulometry(F, 5) == a
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("s_max", [0, 1, 3])
+def test_asf_parity(dtype, shape, s_max):
+    f = image(shape, dtype, seed=shape[1] + s_max)
+    got = host(gc.asf(dev(f), s_max))
+    assert np.array_equal(got, oracle.asf(f, s_max))
+
+
+def test_asf_in_place():
+    f = image((150, 260), np.float64, seed=9)
+    F = dev(f)
+    gc.asf(F, 3, out=F)
+    assert np.array_equal(host(F), oracle.asf(f, 3))
+
+
+def test_full_size_u8_pattern_spectrum_and_asf():
+    f = workloads.operator_u8()
+    check_granulometry(f, 11, "1024x1024 PS[0,11]")
+    assert np.array_equal(host(gc.asf(dev(f), 11)), oracle.asf(f, 11))
