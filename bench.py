@@ -300,7 +300,7 @@ def main():
         for dt_name, dt in (("u8", np.uint8), ("f32", np.float32), ("f64", np.float64)):
             x = torch.from_numpy(workloads.plain_input(dt, size=S)).to(dev)
             y = torch.empty_like(x)
-            for n in (13, 91):
+            for n in (13, 91, 183):
                 ms_p = timed(lambda: gc.dilate_chain(x, n, out=y), max(5, args.steps), 2)
                 extra[f"plain_dilation_{dt_name}_{n}"] = {
                     "gpx_steps_per_s": round(px * n / ms_p / 1e6, 2), "ms": round(ms_p, 4)}

@@ -315,6 +315,20 @@ int gc_geodesic_chain_bwd(gc_dtype dtype, const uint8_t *codes, const void *grad
 int gc_set_tuning(int32_t block_steps, int32_t tile);
 
 /* ---------------------------------------------------------------------
+ * Large-window path for plain chains.  n plain 3x3 steps equal one
+ * (2n+1) x (2n+1) window clipped to the image (Eq. 1-2, 4), computed
+ * separably with the van Herk / Gil-Werman prefix-suffix scheme (the
+ * size-insensitive method the introduction cites) at a cost per pixel that
+ * does not depend on n; results are identical to the chain.  Plain chains
+ * (gc_dilate_chain, gc_erode_chain and the plain chains inside the
+ * composed operators) use it when n_steps >= min_steps and a line plus its
+ * padding fits the kernel's 64 KiB LDS buffer.
+ * min_steps: 0 = built-in crossover (56), -1 = never, > 0 = that threshold.
+ * Process-wide setting.
+ * ------------------------------------------------------------------- */
+int gc_set_window_path(int32_t min_steps);
+
+/* ---------------------------------------------------------------------
  * Measurement hook.  While enabled (on != 0), every kernel launch made by
  * the entry points above is bracketed by two HIP events recorded on the
  * launch stream.  gc_profile_read waits for the last event, returns the sum

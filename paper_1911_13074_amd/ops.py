@@ -221,6 +221,12 @@ def asf(f, s_max, out=None):
     return out
 
 
+def set_window_path(min_steps: int = 0) -> None:
+    """Plain chains of at least min_steps steps run as one separable
+    (2n+1)^2 window (0: built-in threshold, -1: never)."""
+    abi.check(abi.gc_set_window_path(int(min_steps)), "gc_set_window_path")
+
+
 def set_tuning(block_steps: int = 0, tile: int = -1) -> None:
     """Override steps per launch and tile family (0 / -1: built-in choice)."""
     abi.check(abi.gc_set_tuning(int(block_steps), int(tile)), "gc_set_tuning")
