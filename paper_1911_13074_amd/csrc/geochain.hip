@@ -405,17 +405,22 @@ static int copy_image(void *dst, const void *src, const gc_shape &s, size_t es, 
 // ---------------------------------------------------------------------------
 static int g_window_min_steps = 0;   // 0: built-in threshold, -1: never
 // Measured crossover at 1024 x 1024 against the register-blocked chain
-// (u8: window 38 us at any n, chain 37 us at 48 steps and 44 us at 64):
-// below this many steps the chain is at least as fast.
-constexpr int WINDOW_MIN_STEPS_DEFAULT = 56;
+// (u8: window 23-25 us at any n up to 183; chain 22 us at 32 steps and
+// 36 us at 48): below this many steps the chain is at least as fast.
+constexpr int WINDOW_MIN_STEPS_DEFAULT = 40;
 constexpr size_t HGW_LDS_MAX = 65536;
 
-static int64_t hgw_chunks(int64_t length, int64_t n) { return (length + 2 * n + 63) / 64; }
+// Padded positions per lane: odd (distinct LDS banks across lanes) and
+// enough for the line plus n neutral pixels on each side.
+static int64_t hgw_seg(int64_t length, int64_t n) {
+    const int64_t s = (length + 2 * n + 63) / 64;
+    return s | 1;
+}
 
-// LDS of one line: the running extrema (register width) and the line itself.
+// LDS of one line: g and h (register width) and the line itself.
 static size_t hgw_lds_bytes(gc_dtype dtype, int64_t length, int64_t n) {
     const size_t rs = dtype == GC_F64 ? 8 : 4;
-    return (size_t)hgw_chunks(length, n) * 64 * rs + (size_t)length * elem_size(dtype);
+    return (size_t)hgw_seg(length, n) * 64 * 2 * rs + (size_t)length * elem_size(dtype);
 }
 
 static bool window_path(gc_dtype dtype, const gc_shape &s, int64_t n) {
@@ -431,6 +436,21 @@ static bool window_path(gc_dtype dtype, const gc_shape &s, int64_t n) {
     return hgw_lds_bytes(dtype, s.width, nr) <= HGW_LDS_MAX && hgw_lds_bytes(dtype, s.height, nc) <= HGW_LDS_MAX;
 }
 
+// dst (height x width) = transpose of src (width x height).
+template <typename T>
+static void transpose(const T *src, T *dst, int64_t width, int64_t height, int64_t src_pitch, int64_t dst_pitch,
+                      hipStream_t st) {
+    const dim3 grid((unsigned)((width + 63) / 64), (unsigned)((height + 63) / 64));
+    const bool vec = (uintptr_t)src % 16 == 0 && (uintptr_t)dst % 16 == 0 && (src_pitch * (int64_t)sizeof(T)) % 16 == 0 &&
+                     (dst_pitch * (int64_t)sizeof(T)) % 16 == 0;
+    if (vec)
+        hipLaunchKernelGGL((transpose_kernel<T, true>), grid, dim3(256), 0, st, src, dst, (int32_t)width, (int32_t)height,
+                           src_pitch, dst_pitch);
+    else
+        hipLaunchKernelGGL((transpose_kernel<T, false>), grid, dim3(256), 0, st, src, dst, (int32_t)width,
+                           (int32_t)height, src_pitch, dst_pitch);
+}
+
 template <typename T, int OP>
 static int run_window_t(const T *in, T *out, const gc_shape &s, int64_t n, void *stream) {
     using R = typename RegOf<T>::type;
@@ -439,7 +459,10 @@ static int run_window_t(const T *in, T *out, const gc_shape &s, int64_t n, void 
     // A window wider than the image clips to the whole line: radius X-1
     // (Y-1) gives the same result as any larger one.
     const int32_t nr = (int32_t)std::min<int64_t>(n, X - 1), nc = (int32_t)std::min<int64_t>(n, Y - 1);
-    const size_t plane = ((size_t)(X * Y) * sizeof(T) + 255) & ~(size_t)255;
+    // temporaries with pitches rounded to 16 bytes (vector transposes)
+    const int64_t per16 = 16 / (int64_t)sizeof(T);
+    const int64_t px_ = (X + per16 - 1) / per16 * per16, py_ = (Y + per16 - 1) / per16 * per16;
+    const size_t plane = ((size_t)(std::max(px_ * Y, py_ * X)) * sizeof(T) + 255) & ~(size_t)255;
     Workspace *ws = nullptr;
     int rc = get_workspace(stream, 2 * plane, 0, &ws);
     if (rc != GC_OK) return rc;
@@ -452,30 +475,28 @@ static int run_window_t(const T *in, T *out, const gc_shape &s, int64_t n, void 
     r.length = (int32_t)X;
     r.lines = (int32_t)Y;
     r.src_pitch = s.pitch;
-    r.dst_pitch = X;
+    r.dst_pitch = px_;
     r.n = nr;
-    r.chunks = (int32_t)hgw_chunks(X, nr);
+    r.seg = (int32_t)hgw_seg(X, nr);
     int pr = prof_begin(st, 0);
     hipLaunchKernelGGL((hgw_rows_kernel<T, OP>), dim3((unsigned)Y), dim3(64),
-                       r.chunks * 64 * sizeof(R) + X * sizeof(T), st, r);
+                       r.seg * 64 * 2 * sizeof(R) + X * sizeof(T), st, r);
     prof_end(pr, st);
-    hipLaunchKernelGGL((transpose_kernel<T>), dim3((unsigned)((X + 63) / 64), (unsigned)((Y + 63) / 64)), dim3(256),
-                       0, st, (const T *)ta, tb, (int32_t)X, (int32_t)Y, X, Y);
+    transpose(ta, tb, X, Y, px_, py_, st);
     HgwArgs c = r;
     c.src = tb;
     c.dst = ta;
     c.length = (int32_t)Y;
     c.lines = (int32_t)X;
-    c.src_pitch = Y;
-    c.dst_pitch = Y;
+    c.src_pitch = py_;
+    c.dst_pitch = py_;
     c.n = nc;
-    c.chunks = (int32_t)hgw_chunks(Y, nc);
+    c.seg = (int32_t)hgw_seg(Y, nc);
     pr = prof_begin(st, 0);
     hipLaunchKernelGGL((hgw_rows_kernel<T, OP>), dim3((unsigned)X), dim3(64),
-                       c.chunks * 64 * sizeof(R) + Y * sizeof(T), st, c);
+                       c.seg * 64 * 2 * sizeof(R) + Y * sizeof(T), st, c);
     prof_end(pr, st);
-    hipLaunchKernelGGL((transpose_kernel<T>), dim3((unsigned)((Y + 63) / 64), (unsigned)((X + 63) / 64)), dim3(256),
-                       0, st, (const T *)ta, out, (int32_t)Y, (int32_t)X, Y, s.pitch);
+    transpose(ta, out, Y, X, py_, s.pitch, st);
     GC_HIP(hipGetLastError());
     return GC_OK;
 }

@@ -9,15 +9,16 @@
 // padded position s is exactly pick(h[s], g[s + 2n]) -- a cost per pixel
 // that does not depend on n.
 //
-// hgw_rows_kernel: one wave per line, lanes along the line.  Each 64-pixel
-// chunk runs a segmented inclusive scan with DPP (row_shr 1, 2, 4, 8 inside
-// 16-lane rows, then row_bcast 15 and 31 across rows; a lane takes a partner
-// only if the partner lies in its block) and a carry from the previous
-// chunk.  The line is first staged in LDS (its loads all in flight at
-// once); the forward sweep stores g in LDS; the backward sweep reads each
-// chunk in reversed lane order, so the same prefix scan yields h, and emits
-// the outputs of that chunk at once.  Columns go through the same kernel
-// between two tiled transposes (transpose_kernel, 64 x 64 tiles in LDS).
+// hgw_rows_kernel: one wave per line.  The line is staged in LDS (all its
+// loads in flight at once); each lane then owns a contiguous segment of S
+// padded positions (S odd, so the lanes' LDS accesses fall in distinct
+// banks) and runs the running extrema through it sequentially, restarting at
+// block boundaries.  A segmented scan across the 64 lanes (shuffles) gives
+// each segment the extremum carried in from its neighbour, which the
+// positions before the segment's first block boundary then take.  Both g
+// (forward) and h (backward) are built this way in LDS, and the outputs are
+// written coalesced.  Columns go through the same kernel between two tiled
+// transposes (transpose_kernel, 64 x 64 tiles in LDS).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,64 +36,26 @@ struct HgwArgs {
     int64_t src_pitch;   // elements between line starts
     int64_t dst_pitch;
     int32_t n;           // window radius along the line, 0 <= n < length
-    int32_t chunks;      // ceil((length + 2n) / 64)
+    int32_t seg;         // positions per lane: odd, 64 seg >= length + 2n
 };
 
-// DPP move of a register value; lanes that receive nothing keep `old`.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ uint32_t hgw_dpp(uint32_t old, uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, 0xF, false);
-}
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float hgw_dpp(float old, float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
-                                                                 __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xF,
-                                                                 false));
-}
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double hgw_dpp(double old, double v) {
-    const uint64_t o = __builtin_bit_cast(uint64_t, old), u = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)u, CTRL, ROW_MASK,
-                                                              0xF, false);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(u >> 32),
-                                                              CTRL, ROW_MASK, 0xF, false);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-__device__ __forceinline__ uint32_t hgw_lane63(uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, 63); }
-__device__ __forceinline__ float hgw_lane63(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
-}
-__device__ __forceinline__ double hgw_lane63(double v) {
-    const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 63);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-// Inclusive scan of pick over lanes 0..l restricted to the lanes of l's
-// block: o = how many lanes before l (in lane order) belong to its block,
-// capped by nothing (values >= 64 mean "all of them").
-template <int OP, typename R>
-__device__ __forceinline__ R hgw_segmented_scan(R v, int o, int lane) {
+// Segmented inclusive scan over the 64 lanes of (val, flag) pairs, in lane
+// order (FORWARD: lane l combines lanes 0..l) or reversed (lanes l..63):
+// a lane whose flag is set starts a new segment; otherwise it takes the
+// extremum of its value and the scan of the lanes before it.
+template <int OP, bool FORWARD, typename R>
+__device__ __forceinline__ R hgw_lane_scan(R val, int flag) {
     using P = Pick<OP>;
-    const R id = Bounds<R, OP>::bottom();
-    R t;
-    t = hgw_dpp<0x111, 0xF>(id, v);  // row_shr:1
-    v = o >= 1 ? P::pick(v, t) : v;
-    t = hgw_dpp<0x112, 0xF>(id, v);  // row_shr:2
-    v = o >= 2 ? P::pick(v, t) : v;
-    t = hgw_dpp<0x114, 0xF>(id, v);  // row_shr:4
-    v = o >= 4 ? P::pick(v, t) : v;
-    t = hgw_dpp<0x118, 0xF>(id, v);  // row_shr:8
-    v = o >= 8 ? P::pick(v, t) : v;
-    // lane 15 of row r -> every lane of row r + 1 (rows 1 and 3)
-    t = hgw_dpp<0x142, 0xA>(id, v);  // row_bcast:15
-    v = o > (lane & 15) && (lane & 16) ? P::pick(v, t) : v;
-    // lane 31 -> every lane of rows 2 and 3
-    t = hgw_dpp<0x143, 0xC>(id, v);  // row_bcast:31
-    v = o > (lane & 31) && (lane & 32) ? P::pick(v, t) : v;
-    return v;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const R v2 = FORWARD ? __shfl_up(val, d) : __shfl_down(val, d);
+        const int f2 = FORWARD ? __shfl_up(flag, d) : __shfl_down(flag, d);
+        const bool has = FORWARD ? lane >= d : lane + d < 64;
+        if (has && !flag) val = P::pick(val, v2);
+        if (has) flag |= f2;
+    }
+    return val;
 }
 
 template <typename T, int OP>
@@ -100,8 +63,10 @@ __global__ __launch_bounds__(64) void hgw_rows_kernel(HgwArgs a) {
     using R = typename RegOf<T>::type;
     using P = Pick<OP>;
     extern __shared__ unsigned char hgw_lds_raw[];
-    R *g = reinterpret_cast<R *>(hgw_lds_raw);                    // chunks * 64 values
-    T *line_px = reinterpret_cast<T *>(g + a.chunks * 64);        // the line, `length` pixels
+    const int S = a.seg;                                          // positions per lane (odd)
+    R *__restrict__ g = reinterpret_cast<R *>(hgw_lds_raw);       // 64 S running extrema from block starts
+    R *__restrict__ h = reinterpret_cast<R *>(hgw_lds_raw) + 64 * S;   // 64 S running extrema to block ends
+    T *__restrict__ line_px = reinterpret_cast<T *>(reinterpret_cast<R *>(hgw_lds_raw) + 128 * S);
 
     const int line = blockIdx.x;
     const int lane = threadIdx.x;
@@ -111,8 +76,7 @@ __global__ __launch_bounds__(64) void hgw_rows_kernel(HgwArgs a) {
     const int w = 2 * n + 1;
     const R neutral = Bounds<R, OP>::bottom();
 
-    // Stage the line in LDS: all its loads in flight at once, instead of one
-    // exposed memory latency per chunk in the dependent sweeps below.
+    // Stage the line in LDS with all its loads in flight.
     constexpr int U = 8;
     for (int x0 = 0; x0 < a.length; x0 += 64 * U) {
         T vals[U];
@@ -128,63 +92,118 @@ __global__ __launch_bounds__(64) void hgw_rows_kernel(HgwArgs a) {
         }
     }
     __syncthreads();
-
-    // pm = p mod w, advanced by 64 per chunk without a division when w > 64
-    auto step_mod = [&](int pm, int delta) {
-        if (w > 64) {
-            pm += delta;
-            return pm >= w ? pm - w : (pm < 0 ? pm + w : pm);
-        }
-        return ((pm + delta) % w + w) % w;
+    auto padded = [&](int p) {   // the line padded by n neutral pixels each side
+        const int x = p - n;
+        return (unsigned)x < (unsigned)a.length ? to_reg(line_px[x]) : neutral;
     };
 
-    // forward sweep: g (running extremum from each block's start)
-    R carry = neutral;
-    int pm = lane % w;
-    for (int c = 0; c < a.chunks; ++c) {
-        const int p = c * 64 + lane;            // padded position
-        const int x = p - n;
-        const R v = (unsigned)x < (unsigned)a.length ? to_reg(line_px[x]) : neutral;
-        R s = hgw_segmented_scan<OP>(v, pm, lane);   // pm = block lanes before p
-        s = pm > lane ? P::pick(s, carry) : s;       // block started in an earlier chunk
-        g[p] = s;
-        carry = hgw_lane63(s);
-        pm = step_mod(pm, 64);
+    // Each lane owns the padded positions [base, base + S).  Sequential
+    // running extrema inside the segment, restarting at block boundaries;
+    // then the lanes' segment summaries are scanned across lanes and the
+    // positions of each segment that continue a block from a neighbouring
+    // segment take its carry.
+    const int base = lane * S;
+    const int pm0 = base % w;                 // base's offset inside its block
+
+    // forward: g
+    R acc = neutral;
+    int first_start = S;                      // first block start in the segment
+    {
+        int pm = pm0;
+        for (int i = 0; i < S; ++i) {
+            const R v = padded(base + i);
+            const bool start = pm == 0;
+            acc = start ? v : P::pick(acc, v);
+            first_start = (start && first_start == S) ? i : first_start;
+            g[base + i] = acc;
+            pm = pm + 1 == w ? 0 : pm + 1;
+        }
+    }
+    {
+        const R scanned = hgw_lane_scan<OP, true>(acc, first_start < S ? 1 : 0);
+        R carry = __shfl_up(scanned, 1);
+        carry = lane == 0 ? neutral : carry;
+        for (int i = 0; i < first_start; ++i) g[base + i] = P::pick(g[base + i], carry);
+    }
+
+    // backward: h
+    acc = neutral;
+    int last_end = -1;                        // last block end in the segment
+    {
+        int pm = (base + S - 1) % w;
+        for (int i = S - 1; i >= 0; --i) {
+            const R v = padded(base + i);
+            const bool end = pm == w - 1;
+            acc = end ? v : P::pick(acc, v);
+            last_end = (end && last_end < 0) ? i : last_end;
+            h[base + i] = acc;
+            pm = pm == 0 ? w - 1 : pm - 1;
+        }
+    }
+    {
+        const R scanned = hgw_lane_scan<OP, false>(acc, last_end >= 0 ? 1 : 0);
+        R carry = __shfl_down(scanned, 1);
+        carry = lane == 63 ? neutral : carry;
+        for (int i = S - 1; i > last_end; --i) h[base + i] = P::pick(h[base + i], carry);
     }
     __syncthreads();
 
-    // backward sweep in reversed lane order: h (running extremum to each
-    // block's end), and the outputs pick(h[s], g[s + 2n]) for s < length.
-    carry = neutral;
-    pm = ((a.chunks - 1) * 64 + 63 - lane) % w;
-    for (int c = a.chunks - 1; c >= 0; --c) {
-        const int p = c * 64 + 63 - lane;
-        const int x = p - n;
-        const R v = (unsigned)x < (unsigned)a.length ? to_reg(line_px[x]) : neutral;
-        const int o = w - 1 - pm;               // block lanes after p
-        R s = hgw_segmented_scan<OP>(v, o, lane);
-        s = o > lane ? P::pick(s, carry) : s;
-        carry = hgw_lane63(s);
-        if (p < a.length) from_reg(dst + p, P::pick(s, g[p + 2 * n]));
-        pm = step_mod(pm, -64);
-    }
+    // outputs: the window starting at padded position x covers [x, x + 2n]
+    for (int x = lane; x < a.length; x += 64) from_reg(dst + x, P::pick(h[x], g[x + 2 * n]));
 }
 
-// dst (H x W, row = source column) = transpose of src (W x H).
-template <typename T>
-__global__ __launch_bounds__(256) void transpose_kernel(const T *src, T *dst, int32_t width, int32_t height,
-                                                        int64_t src_pitch, int64_t dst_pitch) {
-    __shared__ T tile[64][65];
-    const int bx = blockIdx.x * 64, by = blockIdx.y * 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 64 x 4 threads
-    for (int r = ty; r < 64; r += 4) {
-        const int x = bx + tx, y = by + r;
-        if (x < width && y < height) tile[r][tx] = src[(int64_t)y * src_pitch + x];
-    }
-    __syncthreads();
-    for (int r = ty; r < 64; r += 4) {
-        const int y = by + tx, x = bx + r;   // dst row x, column y
-        if (x < width && y < height) dst[(int64_t)x * dst_pitch + y] = tile[tx][r];
+// dst (H x W, row = source column) = transpose of src (W x H), 64 x 64
+// tiles through LDS.  VEC: every row start of both images is 16-byte
+// aligned, so each thread moves 16 bytes per global access (one tile row of
+// 64 u8, or a quarter / eighth of an f32 / f64 row); otherwise one element.
+template <typename T, bool VEC>
+__global__ __launch_bounds__(256) void transpose_kernel(const T *__restrict__ src, T *__restrict__ dst, int32_t width,
+                                                        int32_t height, int64_t src_pitch, int64_t dst_pitch) {
+    constexpr int TILE = 64;
+    constexpr int PAD = 16 / (int)sizeof(T) > 1 ? 16 / (int)sizeof(T) : 1;
+    __shared__ T tile[TILE][TILE + PAD];
+    const int bx = blockIdx.x * TILE, by = blockIdx.y * TILE;
+    if constexpr (VEC) {
+        constexpr int V = 16 / (int)sizeof(T);         // elements per 16 bytes
+        constexpr int TPR = TILE / V;                   // threads per tile row
+        constexpr int RPI = 256 / TPR;                  // tile rows per iteration
+        const int c0 = (threadIdx.x % TPR) * V;
+        for (int r = threadIdx.x / TPR; r < TILE; r += RPI) {
+            const int y = by + r, x = bx + c0;
+            if (y < height && x + V <= width) {
+                union { uint4 v; T e[V]; } u;
+                u.v = *reinterpret_cast<const uint4 *>(src + (int64_t)y * src_pitch + x);
+#pragma unroll
+                for (int j = 0; j < V; ++j) tile[r][c0 + j] = u.e[j];
+            } else if (y < height) {
+                for (int j = 0; j < V && x + j < width; ++j) tile[r][c0 + j] = src[(int64_t)y * src_pitch + x + j];
+            }
+        }
+        __syncthreads();
+        // dst row = source column bx + r; its elements by .. by + 63
+        for (int r = threadIdx.x / TPR; r < TILE; r += RPI) {
+            const int x = bx + r, y = by + c0;
+            if (x >= width) continue;
+            if (y + V <= height) {
+                union { uint4 v; T e[V]; } u;
+#pragma unroll
+                for (int j = 0; j < V; ++j) u.e[j] = tile[c0 + j][r];
+                *reinterpret_cast<uint4 *>(dst + (int64_t)x * dst_pitch + y) = u.v;
+            } else {
+                for (int j = 0; j < V && y + j < height; ++j) dst[(int64_t)x * dst_pitch + y + j] = tile[c0 + j][r];
+            }
+        }
+    } else {
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 64 x 4 threads
+        for (int r = ty; r < TILE; r += 4) {
+            const int x = bx + tx, y = by + r;
+            if (x < width && y < height) tile[r][tx] = src[(int64_t)y * src_pitch + x];
+        }
+        __syncthreads();
+        for (int r = ty; r < TILE; r += 4) {
+            const int y = by + tx, x = bx + r;
+            if (x < width && y < height) dst[(int64_t)x * dst_pitch + y] = tile[tx][r];
+        }
     }
 }
 
