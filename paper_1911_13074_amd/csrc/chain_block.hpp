@@ -267,75 +267,100 @@ __device__ __forceinline__ uint32_t chain_block_body(const BlockArgs &a, int rx0
 
     // Only waves holding core rows track changes; the others run the same
     // steps without the comparisons (one loop per case, each branch-free).
+    //
+    // The steps are software-pipelined across the barrier: after the column
+    // pass of step s, a wave first computes the row pass of its two edge rows
+    // for step s+1, publishes them (LDS write, barrier, LDS reads of the
+    // neighbours' edges) and only then does the row pass of its middle rows
+    // and, in the next iteration, their column pass -- work that needs no
+    // LDS data and so covers the latency of the reads.  Every wave still
+    // takes exactly k barriers.
     const bool wave_has_core = DETECT && w * RPW + RPW > halo && w * RPW < halo + a.core_y;
     auto run_steps = [&](auto detect_tag) {
         constexpr bool D = decltype(detect_tag)::value;
-        for (int s = 0; s < busy; ++s) {
-            // ---- 1. row pass ----
-            R h[RPW][CW];
+        if (busy == 0) return;
+        R h[RPW][CW];
+        R above[CW], below[CW];
+        const int wa = w > 0 ? w - 1 : NW - 1;   // the first / last wave reads its own
+        const int wb = w < NW - 1 ? w + 1 : 0;   // opposite edge: wrong, but on the region's edge
+        // ---- row pass of one row (Section 3.1) ----
+        auto row_pass = [&](int r) {
+            const R left = lane_shift<DPP_WAVE_SHR1>(v[r][CW - 1]);
+            const R right = lane_shift<DPP_WAVE_SHL1>(v[r][0]);
+            if constexpr (CW == 1) {
+                h[r][0] = P::pick(P::pick(left, v[r][0]), right);
+            } else if constexpr (CW == 2) {
+                // The pair's own extremum is shared by both outputs; each
+                // output then takes one cross-lane neighbour, which the
+                // compiler folds into a single DPP-sourced max/min.
+                const R t = P::pick(v[r][0], v[r][1]);
+                h[r][0] = P::pick(t, left);
+                h[r][1] = P::pick(t, right);
+            } else {
 #pragma unroll
-            for (int r = 0; r < RPW; ++r) {
-                const R left = lane_shift<DPP_WAVE_SHR1>(v[r][CW - 1]);
-                const R right = lane_shift<DPP_WAVE_SHL1>(v[r][0]);
-                if constexpr (CW == 1) {
-                    h[r][0] = P::pick(P::pick(left, v[r][0]), right);
-                } else if constexpr (CW == 2) {
-                    // The pair's own extremum is shared by both outputs; each
-                    // output then takes one cross-lane neighbour, which the
-                    // compiler folds into a single DPP-sourced max/min.
-                    const R t = P::pick(v[r][0], v[r][1]);
-                    h[r][0] = P::pick(t, left);
-                    h[r][1] = P::pick(t, right);
-                } else {
-#pragma unroll
-                    for (int c = 0; c < CW; ++c) {
-                        const R l = c == 0 ? left : v[r][c - 1];
-                        const R rr = c == CW - 1 ? right : v[r][c + 1];
-                        h[r][c] = P::pick(P::pick(v[r][c], rr), l);
-                    }
+                for (int c = 0; c < CW; ++c) {
+                    const R l = c == 0 ? left : v[r][c - 1];
+                    const R rr = c == CW - 1 ? right : v[r][c + 1];
+                    h[r][c] = P::pick(P::pick(v[r][c], rr), l);
                 }
             }
-            // ---- 2. exchange edge rows with the waves above and below ----
-            const int par = s & 1;
+        };
+        // ---- edge rows to the waves above and below, through LDS ----
+        auto publish = [&](int par) {
 #pragma unroll
             for (int c = 0; c < CW; ++c) {
                 xch[par][w][0][lane * CW + c] = h[0][c];
                 xch[par][w][1][lane * CW + c] = h[RPW - 1][c];
             }
             __syncthreads();
-            // The first (last) wave has no wave above (below); it reads its own
-            // opposite edge instead, a wrong but harmless value on the region's
-            // outer edge.  Branch-free, so the whole step is one basic block.
-            const int wa = w > 0 ? w - 1 : NW - 1;
-            const int wb = w < NW - 1 ? w + 1 : 0;
-            R above[CW], below[CW];
 #pragma unroll
             for (int c = 0; c < CW; ++c) {
                 above[c] = xch[par][wa][1][lane * CW + c];
                 below[c] = xch[par][wb][0][lane * CW + c];
             }
-            // ---- 3. column pass + clamp ----
+        };
+        // ---- column pass + clamp of one row ----
+        auto column_pass = [&](int r, R (&nv)[RPW][CW], uint64_t &changed) {
+            const int ry = w * RPW + r;
+            const bool row_in_core = D && ry >= halo && ry < halo + a.core_y && ry0 + ry < a.height;
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                const R up = r == 0 ? above[c] : h[r - 1][c];
+                const R dn = r == RPW - 1 ? below[c] : h[r + 1][c];
+                R x = P::pick(P::pick(up, h[r][c]), dn);
+                if constexpr (CLAMP) x = P::clamp(x, m[r][c]);
+                if constexpr (D) {
+                    // branch-free: a uniform row mask instead of an if
+                    const uint64_t row_mask = row_in_core ? ~0ull : 0ull;
+                    changed |= __builtin_amdgcn_ballot_w64(x != v[r][c]) & col_in_core[c] & row_mask;
+                }
+                nv[r][c] = x;
+            }
+        };
+
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) row_pass(r);
+        publish(0);
+        for (int s = 0; s < busy; ++s) {
+            R nv[RPW][CW];
             uint64_t changed = 0;
 #pragma unroll
-            for (int r = 0; r < RPW; ++r) {
-                const int ry = w * RPW + r;
-                const bool row_in_core = D && ry >= halo && ry < halo + a.core_y && ry0 + ry < a.height;
+            for (int r = 1; r < RPW - 1; ++r) column_pass(r, nv, changed);
+            column_pass(0, nv, changed);
+            if constexpr (RPW > 1) column_pass(RPW - 1, nv, changed);
 #pragma unroll
-                for (int c = 0; c < CW; ++c) {
-                    const R up = r == 0 ? above[c] : h[r - 1][c];
-                    const R dn = r == RPW - 1 ? below[c] : h[r + 1][c];
-                    R nv = P::pick(P::pick(up, h[r][c]), dn);
-                    if constexpr (CLAMP) nv = P::clamp(nv, m[r][c]);
-                    if constexpr (D) {
-                        // branch-free: a uniform row mask instead of an if
-                        const uint64_t row_mask = row_in_core ? ~0ull : 0ull;
-                        changed |= __builtin_amdgcn_ballot_w64(nv != v[r][c]) & col_in_core[c] & row_mask;
-                    }
-                    v[r][c] = nv;
-                }
-            }
+            for (int r = 0; r < RPW; ++r)
+#pragma unroll
+                for (int c = 0; c < CW; ++c) v[r][c] = nv[r][c];
             if constexpr (D) {
                 if (changed) step_bits |= 1u << s;
+            }
+            if (s + 1 < busy) {
+                row_pass(0);
+                if constexpr (RPW > 1) row_pass(RPW - 1);
+                publish((s + 1) & 1);
+#pragma unroll
+                for (int r = 1; r < RPW - 1; ++r) row_pass(r);
             }
         }
     };

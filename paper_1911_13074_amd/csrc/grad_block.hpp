@@ -31,8 +31,9 @@
 //
 // Layout: lane = region column (64 per region), wave w = region rows
 // [8w, 8w + 8).  Each lane walks its 8 rows keeping the row-pass results (or
-// codes and gradients) of three rows on a rolling window, so a step costs
-// three LDS reads per pixel and array.  After step s of k only the band
+// codes and gradients) of three rows on a rolling window; the left and right
+// columns come from the adjacent lanes by DPP, so a step costs one LDS read
+// per pixel and array.  After step s of k only the band
 // within k-1-s of the core is still needed; waves outside it skip.  One
 // launch covers a batch of images (grid.z = image).
 #pragma once
@@ -50,6 +51,27 @@ constexpr uint8_t CODE_NONE = 255;
 template <int OP, typename T>
 __device__ __forceinline__ bool better(T a, T b) {
     return OP == OP_DILATE ? (a > b) : (a < b);
+}
+
+// Value of the adjacent lane (lane = region column): WAVE_SHR1 gives column
+// x - 1, WAVE_SHL1 column x + 1.  Lanes 0 / 63 receive 0: they are the
+// region's outer columns, whose results are wrong anyway and never reach the
+// core (an error moves one column per step, the core starts GB_K columns in).
+// Zero fill lets the compiler fold the shift into the consuming compare/add.
+template <int CTRL>
+__device__ __forceinline__ int gb_shift(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ __forceinline__ float gb_shift(float v) {
+    return __builtin_bit_cast(float, gb_shift<CTRL>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double gb_shift(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)gb_shift<CTRL>((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)gb_shift<CTRL>((int)(uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 // Region: GB_RW = 64 columns, one per lane; wave w holds rows [8w, 8w + 8).
@@ -115,7 +137,6 @@ __global__ __launch_bounds__(GradTile<T>::THREADS) void block_codes_kernel(GradB
     const int rx0 = x0 - GB_K, ry0 = y0 - GB_K;               // region origin
     const int x = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int xl = max(x - 1, 0), xr = min(x + 1, GB_RW - 1);  // edge lanes: harmless repeats
     const int gx = rx0 + x;
     const bool xin = (unsigned)gx < (unsigned)a.width;
 
@@ -140,9 +161,10 @@ __global__ __launch_bounds__(GradTile<T>::THREADS) void block_codes_kernel(GradB
         if (w * GB_WR + GB_WR > lo && w * GB_WR < hi_r) {
             // row pass (value, dx index) of rows y-1, y, y+1 on a rolling window
             auto row_pass = [&](int ly, T &v, int &ix) {
-                v = sf[cur][ly][xl];
+                const T c = sf[cur][ly][x];
+                v = gb_shift<DPP_WAVE_SHR1>(c);
+                const T r = gb_shift<DPP_WAVE_SHL1>(c);
                 ix = 0;
-                const T c = sf[cur][ly][x], r = sf[cur][ly][xr];
                 if (better<OP>(c, v)) { v = c; ix = 1; }
                 if (better<OP>(r, v)) { v = r; ix = 2; }
             };
@@ -197,7 +219,6 @@ __global__ __launch_bounds__(GradTile<T>::THREADS) void block_bwd_kernel(GradBlo
     const int rx0 = x0 - GB_K, ry0 = y0 - GB_K;
     const int x = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int xl = max(x - 1, 0), xr = min(x + 1, GB_RW - 1);
     const int gx = rx0 + x;
     const bool xin = (unsigned)gx < (unsigned)a.width;
     const int k = a.k;
@@ -248,12 +269,15 @@ __global__ __launch_bounds__(GradTile<T>::THREADS) void block_bwd_kernel(GradBlo
         if (w * GB_WR + GB_WR > lo && w * GB_WR < hi_r) {
             // rolling window of (code, gradient) at columns x-1, x, x+1 of
             // rows y-1, y, y+1
-            auto load_row = [&](int ly, uint8_t *c, T *g) {
-                c[0] = scd[s][ly][xl]; g[0] = sg[cur][ly][xl];
-                c[1] = scd[s][ly][x];  g[1] = sg[cur][ly][x];
-                c[2] = scd[s][ly][xr]; g[2] = sg[cur][ly][xr];
+            auto load_row = [&](int ly, int *c, T *g) {
+                c[1] = scd[s][ly][x];
+                g[1] = sg[cur][ly][x];
+                c[0] = gb_shift<DPP_WAVE_SHR1>(c[1]);
+                g[0] = gb_shift<DPP_WAVE_SHR1>(g[1]);
+                c[2] = gb_shift<DPP_WAVE_SHL1>(c[1]);
+                g[2] = gb_shift<DPP_WAVE_SHL1>(g[1]);
             };
-            uint8_t c0[3], c1[3], c2[3];
+            int c0[3], c1[3], c2[3];
             T g0[3], g1[3], g2[3];
             load_row(max(w * GB_WR - 1, 0), c0, g0);
             load_row(w * GB_WR, c1, g1);
