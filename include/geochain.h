@@ -323,7 +323,8 @@ int gc_set_tuning(int32_t block_steps, int32_t tile);
  * (gc_dilate_chain, gc_erode_chain and the plain chains inside the
  * composed operators) use it when n_steps >= min_steps and a line plus its
  * padding fits the kernel's 64 KiB LDS buffer.
- * min_steps: 0 = built-in crossover (40), -1 = never, > 0 = that threshold.
+ * min_steps: 0 = built-in crossover (26 steps for u8, 34 for f32, 38 for
+ * f64), -1 = never, > 0 = that threshold.
  * Process-wide setting.
  * ------------------------------------------------------------------- */
 int gc_set_window_path(int32_t min_steps);

@@ -404,17 +404,28 @@ static int copy_image(void *dst, const void *src, const gc_shape &s, size_t es, 
 // large windows: plain chains as one (2n+1)^2 window (van Herk / Gil-Werman)
 // ---------------------------------------------------------------------------
 static int g_window_min_steps = 0;   // 0: built-in threshold, -1: never
-// Measured crossover at 1024 x 1024 against the register-blocked chain
-// (u8: window 23-25 us at any n up to 183; chain 22 us at 32 steps and
-// 36 us at 48): below this many steps the chain is at least as fast.
-constexpr int WINDOW_MIN_STEPS_DEFAULT = 40;
+// Measured crossovers at 1024 x 1024 against the register-blocked chain:
+// the window path takes 18-19 us (u8), 24-25 us (f32), 34-36 us (f64) at
+// any n up to 183; the chain 19 / 20 / 25 us at 24 steps and 22 / 22 / 30 us
+// at 32.  Below these many steps the chain is at least as fast.
+static int window_min_steps_default(gc_dtype dtype) {
+    switch (dtype) {
+        case GC_U8: return 26;
+        case GC_F32: return 34;
+        default: return 38;
+    }
+}
 constexpr size_t HGW_LDS_MAX = 65536;
 
 // Padded positions per lane: odd (distinct LDS banks across lanes) and
-// enough for the line plus n neutral pixels on each side.
+// enough for the line plus n neutral pixels on each side; rounded up to a
+// length the register kernel is compiled for when one fits.
+static const int HGW_REG_SEGS[] = {9, 17, 25, 33, 49, 65};
 static int64_t hgw_seg(int64_t length, int64_t n) {
-    const int64_t s = (length + 2 * n + 63) / 64;
-    return s | 1;
+    const int64_t s = ((length + 2 * n + 63) / 64) | 1;
+    for (int r : HGW_REG_SEGS)
+        if (s <= r) return r;
+    return s;
 }
 
 // LDS of one line: g and h (register width) and the line itself.
@@ -430,10 +441,27 @@ static bool window_path(gc_dtype dtype, const gc_shape &s, int64_t n) {
         thr = g_window_min_steps;
     }
     if (thr < 0) return false;
-    if (thr == 0) thr = WINDOW_MIN_STEPS_DEFAULT;
+    if (thr == 0) thr = window_min_steps_default(dtype);
     if (n < thr) return false;
     const int64_t nr = std::min<int64_t>(n, s.width - 1), nc = std::min<int64_t>(n, s.height - 1);
     return hgw_lds_bytes(dtype, s.width, nr) <= HGW_LDS_MAX && hgw_lds_bytes(dtype, s.height, nc) <= HGW_LDS_MAX;
+}
+
+// One line per wave: the register kernel when a lane's segment fits it.
+template <typename T, int OP>
+static void hgw_rows(const HgwArgs &a, unsigned lines, size_t lds, hipStream_t st) {
+    switch (a.seg) {
+#define GC_HGW_REG(S_) \
+    case S_: hipLaunchKernelGGL((hgw_rows_reg_kernel<T, OP, S_>), dim3(lines), dim3(64), lds, st, a); return;
+        GC_HGW_REG(9)
+        GC_HGW_REG(17)
+        GC_HGW_REG(25)
+        GC_HGW_REG(33)
+        GC_HGW_REG(49)
+        GC_HGW_REG(65)
+#undef GC_HGW_REG
+        default: hipLaunchKernelGGL((hgw_rows_kernel<T, OP>), dim3(lines), dim3(64), lds, st, a);
+    }
 }
 
 // dst (height x width) = transpose of src (width x height).
@@ -479,8 +507,7 @@ static int run_window_t(const T *in, T *out, const gc_shape &s, int64_t n, void 
     r.n = nr;
     r.seg = (int32_t)hgw_seg(X, nr);
     int pr = prof_begin(st, 0);
-    hipLaunchKernelGGL((hgw_rows_kernel<T, OP>), dim3((unsigned)Y), dim3(64),
-                       r.seg * 64 * 2 * sizeof(R) + X * sizeof(T), st, r);
+    hgw_rows<T, OP>(r, (unsigned)Y, r.seg * 64 * 2 * sizeof(R) + X * sizeof(T), st);
     prof_end(pr, st);
     transpose(ta, tb, X, Y, px_, py_, st);
     HgwArgs c = r;
@@ -493,8 +520,7 @@ static int run_window_t(const T *in, T *out, const gc_shape &s, int64_t n, void 
     c.n = nc;
     c.seg = (int32_t)hgw_seg(Y, nc);
     pr = prof_begin(st, 0);
-    hipLaunchKernelGGL((hgw_rows_kernel<T, OP>), dim3((unsigned)X), dim3(64),
-                       c.seg * 64 * 2 * sizeof(R) + Y * sizeof(T), st, c);
+    hgw_rows<T, OP>(c, (unsigned)X, c.seg * 64 * 2 * sizeof(R) + Y * sizeof(T), st);
     prof_end(pr, st);
     transpose(ta, out, Y, X, py_, s.pitch, st);
     GC_HIP(hipGetLastError());

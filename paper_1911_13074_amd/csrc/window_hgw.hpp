@@ -24,6 +24,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "chain_block.hpp"
 
 namespace geochain {
@@ -38,6 +40,27 @@ struct HgwArgs {
     int32_t n;           // window radius along the line, 0 <= n < length
     int32_t seg;         // positions per lane: odd, 64 seg >= length + 2n
 };
+
+// DPP move of a register value; lanes that receive nothing keep `old`.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t hgw_dpp(uint32_t old, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float hgw_dpp(float old, float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                                 __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xF,
+                                                                 false));
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double hgw_dpp(double old, double v) {
+    const uint64_t o = __builtin_bit_cast(uint64_t, old), u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)u, CTRL, ROW_MASK,
+                                                              0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(u >> 32),
+                                                              CTRL, ROW_MASK, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
 
 // Segmented inclusive scan over the 64 lanes of (val, flag) pairs, in lane
 // order (FORWARD: lane l combines lanes 0..l) or reversed (lanes l..63):
@@ -149,6 +172,121 @@ __global__ __launch_bounds__(64) void hgw_rows_kernel(HgwArgs a) {
     __syncthreads();
 
     // outputs: the window starting at padded position x covers [x, x + 2n]
+    for (int x = lane; x < a.length; x += 64) from_reg(dst + x, P::pick(h[x], g[x + 2 * n]));
+}
+
+// Inclusive segmented scan in lane order by DPP: a lane whose flag is set
+// starts a segment; otherwise it takes the extremum of its value and the
+// scan of the lanes before it.  row_shr 1, 2, 4, 8 scan each 16-lane row,
+// row_bcast 15 and 31 then carry rows 0 and 0-1 into the rows after them.
+template <int OP, typename R>
+__device__ __forceinline__ R hgw_flag_scan(R val, int flag) {
+    using P = Pick<OP>;
+    const R id = Bounds<R, OP>::bottom();
+    auto step = [&](auto ctrl_tag, auto mask_tag) {
+        constexpr int CTRL = decltype(ctrl_tag)::value, MASK = decltype(mask_tag)::value;
+        const R t = hgw_dpp<CTRL, MASK>(id, val);
+        const int tf = (int)hgw_dpp<CTRL, MASK>(0u, (uint32_t)flag);
+        val = flag ? val : P::pick(val, t);
+        flag |= tf;
+    };
+    step(std::integral_constant<int, 0x111>{}, std::integral_constant<int, 0xF>{});
+    step(std::integral_constant<int, 0x112>{}, std::integral_constant<int, 0xF>{});
+    step(std::integral_constant<int, 0x114>{}, std::integral_constant<int, 0xF>{});
+    step(std::integral_constant<int, 0x118>{}, std::integral_constant<int, 0xF>{});
+    step(std::integral_constant<int, 0x142>{}, std::integral_constant<int, 0xA>{});
+    step(std::integral_constant<int, 0x143>{}, std::integral_constant<int, 0xC>{});
+    return val;
+}
+
+// The same line window with each lane's segment held in registers: the
+// segment length S is the compile-time constant (the host pads the line to
+// 64 S positions with neutral values), so every loop unrolls without guards
+// and each sweep's LDS reads go out as one batch instead of one dependent
+// read per position.  The backward sweep gives lane l the segment 63 - l, so
+// its scan across lanes also runs in lane order.
+template <typename T, int OP, int S>
+__global__ __launch_bounds__(64) void hgw_rows_reg_kernel(HgwArgs a) {
+    using R = typename RegOf<T>::type;
+    using P = Pick<OP>;
+    extern __shared__ unsigned char hgw_lds_raw[];
+    R *__restrict__ g = reinterpret_cast<R *>(hgw_lds_raw);
+    R *__restrict__ h = reinterpret_cast<R *>(hgw_lds_raw) + 64 * S;
+    T *__restrict__ line_px = reinterpret_cast<T *>(reinterpret_cast<R *>(hgw_lds_raw) + 128 * S);
+
+    const int line = blockIdx.x;
+    const int lane = threadIdx.x;
+    const T *src = static_cast<const T *>(a.src) + (int64_t)line * a.src_pitch;
+    T *dst = static_cast<T *>(a.dst) + (int64_t)line * a.dst_pitch;
+    const int n = a.n;
+    const int w = 2 * n + 1;
+    const R neutral = Bounds<R, OP>::bottom();
+
+    constexpr int U = 8;
+    for (int x0 = 0; x0 < a.length; x0 += 64 * U) {
+        T vals[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int x = x0 + u * 64 + lane;
+            vals[u] = x < a.length ? src[x] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int x = x0 + u * 64 + lane;
+            if (x < a.length) line_px[x] = vals[u];
+        }
+    }
+    __syncthreads();
+    auto padded = [&](int p) {
+        const int x = p - n;
+        return (unsigned)x < (unsigned)a.length ? to_reg(line_px[x]) : neutral;
+    };
+
+    // forward: lane l owns segment l
+    {
+        const int base = lane * S;
+        R v[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) v[i] = padded(base + i);
+        R acc = neutral;
+        int first_start = S;
+        int pm = base % w;
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            const bool start = pm == 0;
+            acc = start ? v[i] : P::pick(acc, v[i]);
+            first_start = (start && first_start == S) ? i : first_start;
+            v[i] = acc;
+            pm = pm + 1 == w ? 0 : pm + 1;
+        }
+        const R scanned = hgw_flag_scan<OP>(acc, first_start < S ? 1 : 0);
+        const R carry = hgw_dpp<DPP_WAVE_SHR1, 0xF>(neutral, scanned);   // lane l - 1's, lane 0: neutral
+#pragma unroll
+        for (int i = 0; i < S; ++i) g[base + i] = i < first_start ? P::pick(v[i], carry) : v[i];
+    }
+    // backward: lane l owns segment 63 - l, scanned from its end
+    {
+        const int base = (63 - lane) * S;
+        R v[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) v[i] = padded(base + i);
+        R acc = neutral;
+        int last_end = -1;
+        int pm = (base + S - 1) % w;
+#pragma unroll
+        for (int i = S - 1; i >= 0; --i) {
+            const bool end = pm == w - 1;
+            acc = end ? v[i] : P::pick(acc, v[i]);
+            last_end = (end && last_end < 0) ? i : last_end;
+            v[i] = acc;
+            pm = pm == 0 ? w - 1 : pm - 1;
+        }
+        const R scanned = hgw_flag_scan<OP>(acc, last_end >= 0 ? 1 : 0);
+        const R carry = hgw_dpp<DPP_WAVE_SHR1, 0xF>(neutral, scanned);   // the segment to the right
+#pragma unroll
+        for (int i = 0; i < S; ++i) h[base + i] = i > last_end ? P::pick(v[i], carry) : v[i];
+    }
+    __syncthreads();
     for (int x = lane; x < a.length; x += 64) from_reg(dst + x, P::pick(h[x], g[x + 2 * n]));
 }
 
