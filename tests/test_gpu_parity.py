@@ -260,3 +260,32 @@ def test_repeat_determinism():
     a = host(gc.geodesic_dilate_chain(F, M, 777))
     for _ in range(3):
         assert np.array_equal(host(gc.geodesic_dilate_chain(F, M, 777)), a)
+
+
+# --------------------------------------------------------------------------
+# maximum sizes: more than 2^31 pixels per image
+# --------------------------------------------------------------------------
+def test_image_beyond_2_31_pixels_sampled():
+    """46341 x 46341 u8 (2.15e9 pixels per image; element offsets beyond
+    2^31), 40 geodesic dilations.  After n steps a pixel depends only on the
+    marker and mask within chessboard distance n, so the oracle on a crop
+    reaching n pixels past it (or to the image edge) gives it exactly; 40
+    sampled pixels, corners and edges included."""
+    side, n = 46341, 40
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    F = torch.randint(0, 200, (side, side), dtype=torch.uint8, device="cuda", generator=gen)
+    M = torch.randint(50, 256, (side, side), dtype=torch.uint8, device="cuda", generator=gen)
+    out = gc.geodesic_dilate_chain(F, M, n)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    pts = [(0, 0), (0, side - 1), (side - 1, 0), (side - 1, side - 1), (side // 2, 0), (0, side // 2)]
+    pts += [tuple(int(v) for v in rng.integers(0, side, 2)) for _ in range(34)]
+    for y, x in pts:
+        y0, y1 = max(0, y - n), min(side, y + n + 1)
+        x0, x1 = max(0, x - n), min(side, x + n + 1)
+        f = F[y0:y1, x0:x1].cpu().numpy()
+        m = M[y0:y1, x0:x1].cpu().numpy()
+        ref = oracle.chain(oracle.DILATE, f, n, m)[y - y0, x - x0]
+        assert int(out[y, x]) == int(ref), (y, x)
+    del F, M, out
+    torch.cuda.empty_cache()

@@ -83,6 +83,17 @@ def test_window_padded_pitch_and_in_place(dtype):
     assert torch.all(F[:, w:] == 0)
 
 
+@pytest.mark.parametrize("dtype", [np.uint8, np.float32])
+def test_long_lines_take_the_segment_loop_kernel(dtype):
+    # 5000 + 2 * 50 padded pixels need 81 positions per lane: beyond the
+    # register variants (up to 65), within the loop kernel's LDS buffer
+    f = rand((3, 5000), dtype, seed=4)
+    for op in OPS:
+        assert np.array_equal(host(run(op, dev(f), 50)), oracle.chain(op, f, 50))
+    g = rand((4800, 5), dtype, seed=5)
+    assert np.array_equal(host(run(oracle.DILATE, dev(g), 60)), oracle.chain(oracle.DILATE, g, 60))
+
+
 def test_lines_too_long_for_the_window_path_run_as_chains():
     # 30000 pixels per line exceed the path's LDS line buffer
     f = rand((3, 30000), np.uint8, seed=2)
