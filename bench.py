@@ -111,20 +111,24 @@ def profiled_traffic():
     return int(vals["traffic_bytes_per_dispatch"]), float(vals["avg_dispatch_ns"]) * 1e-6
 
 
-def cpu_baseline(f, m, n_steps):
+def cpu_baseline(f, m, n_steps, repeats=3):
+    """The oracle, as it stands, on the benchmark workload: `repeats` runs
+    of the whole chain (about 1.5 s on 16 host threads, i.e. some 20 s of
+    CPU work), reported as the mean rate."""
     import oracle
     threads = oracle.max_threads()
     t0 = time.perf_counter()
-    oracle.chain(oracle.DILATE, f, n_steps, m)
-    dt = time.perf_counter() - t0
+    for _ in range(repeats):
+        oracle.chain(oracle.DILATE, f, n_steps, m)
+    dt = (time.perf_counter() - t0) / repeats
     return {
         "value": round(f.size * n_steps / dt / 1e9, 4),
         "unit": "Gpixel-steps/s",
         "cores": threads,
         "kind": "oracle",
         "sample": f"{f.shape[0]}x{f.shape[1]} u8, {n_steps}-step geodesic dilation chain "
-                  f"(the benchmark workload, {n_steps} of its steps), plain C oracle, "
-                  f"OpenMP over rows, {dt:.2f} s",
+                  f"(the benchmark workload in full), {repeats} runs of the plain C oracle, "
+                  f"OpenMP over rows on {threads} threads, {dt:.2f} s per run",
     }
 
 
