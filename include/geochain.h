@@ -16,8 +16,17 @@
  *                    reached at the first step that changes no pixel
  *                    (convergence test of Section 3.7, Algorithm 5).
  *
- * Every result is exact: the steps only select existing values, so u8,
- * f32 and f64 results are bit-identical to the definitions.  NaN inputs are
+ * On these the library builds the operators of Section 2: H-maxima, dome
+ * extraction, hole filling, removal of border objects and opening by
+ * reconstruction (Eq. 6-12), the quasi-distance transform (Eq. 13-15,
+ * Algorithm 6), granulometry, pattern spectrum and alternating sequential
+ * filters (Eq. 16-20); plus, beyond the paper, batches of chains in one
+ * persistent launch and the gradient of a chain.
+ *
+ * Chains, reconstructions and plain windows are exact: the steps only
+ * select existing values, so u8, f32 and f64 results are bit-identical to
+ * the definitions.  Where an operator subtracts, it does so once in the
+ * image's dtype, as stated at its declaration.  NaN inputs are
  * outside the definitions and give unspecified (but memory-safe) results;
  * -0.0 and +0.0 compare equal and either may be returned.
  *

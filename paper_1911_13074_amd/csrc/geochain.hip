@@ -1165,7 +1165,7 @@ struct PlanChoice {
 // the autotuner when every item's size class has an entry, else built-in.
 static PlanChoice choose_plan_batch(gc_dtype d, int op, int mode, const std::vector<gc_item> &items) {
     PlanChoice c;
-    c.fam = FAM_128;
+    c.fam = FAM_128W;   // measured best for the 64-image uneven batch (k = 20, two workgroups per CU)
     int forced_k = 0, forced_fam = -1;
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
