@@ -592,6 +592,245 @@ __device__ __forceinline__ uint32_t chain_block_body_g2(const BlockArgs &a, int 
 }
 
 // Lanes per column group: 64 (one group) or 32 (two groups).
+// ---------------------------------------------------------------------------
+// u8 body with two rows per register.  Register row j of a wave holds its
+// region rows j (low 16 bits) and j + RPW/2 (high 16 bits), so each packed
+// 16-bit max/min handles two pixels; both rows belong to the same wave, so
+// the busy band, the edge exchange and the row pass are those of
+// chain_block_body.  The column pass meets the halves' seams twice: the row
+// above register 0's low half is the wave above's last row (the high half of
+// its last register) and the row above its high half is this wave's
+// register RPW/2 - 1, low half; one funnel shift (alignbit) builds each seam
+// operand, and likewise below the last register.  Pixel values stay in
+// 0..255, so every 16-bit lane holds an exact u8 value.
+// ---------------------------------------------------------------------------
+typedef unsigned short gc_u16x2 __attribute__((ext_vector_type(2)));
+
+template <int OP> struct PackedPick;
+template <> struct PackedPick<OP_DILATE> {
+    static __device__ __forceinline__ uint32_t pick(uint32_t a, uint32_t b) {
+        return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(gc_u16x2, a),
+                                                                      __builtin_bit_cast(gc_u16x2, b)));
+    }
+    static __device__ __forceinline__ uint32_t clamp(uint32_t a, uint32_t b) {
+        return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(gc_u16x2, a),
+                                                                      __builtin_bit_cast(gc_u16x2, b)));
+    }
+};
+template <> struct PackedPick<OP_ERODE> {
+    static __device__ __forceinline__ uint32_t pick(uint32_t a, uint32_t b) {
+        return PackedPick<OP_DILATE>::clamp(a, b);
+    }
+    static __device__ __forceinline__ uint32_t clamp(uint32_t a, uint32_t b) {
+        return PackedPick<OP_DILATE>::pick(a, b);
+    }
+};
+
+__device__ __forceinline__ uint32_t pack_rows(uint32_t lo, uint32_t hi) { return lo | (hi << 16); }
+
+template <int OP, int MODE, bool CLAMP, bool DETECT, int RPW, int NW>
+__device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int rx0, int ry0,
+                                                        uint32_t (*xch)[NW][2][128]) {
+    static_assert(RPW % 2 == 0, "two rows per register");
+    constexpr int H = RPW / 2;      // registers per column
+    constexpr int CW = 2;
+    using B = Bounds<uint32_t, OP>;
+    using P = PackedPick<OP>;
+
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint8_t *src = static_cast<const uint8_t *>(a.src);
+    const uint8_t *msk = static_cast<const uint8_t *>(a.mask);
+    uint8_t *dst = static_cast<uint8_t *>(a.dst);
+    const int k = a.k;
+    const int halo = a.halo;
+    constexpr int RX = 64 * CW;
+    constexpr int RY = NW * RPW;
+
+    uint32_t v[H][CW];
+    uint32_t m[CLAMP ? H : 1][CW];
+
+    // ---- load region (rows j and j + H into register j) ----
+    const bool fast = rx0 >= 0 && ry0 >= 0 && rx0 + RX <= a.width && ry0 + RY <= a.height && (rx0 & 1) == 0 &&
+                      (a.pitch & 1) == 0 && pair_aligned(src) && (MODE != MODE_GEODESIC || pair_aligned(msk));
+    if (fast) {
+        const int64_t base = (int64_t)(ry0 + w * RPW) * a.pitch + rx0 + lane * 2;
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const uint32_t lo = *reinterpret_cast<const uint16_t *>(src + base + j * a.pitch);
+            const uint32_t hi = *reinterpret_cast<const uint16_t *>(src + base + (j + H) * a.pitch);
+            v[j][0] = pack_rows(lo & 0xFFu, hi & 0xFFu);
+            v[j][1] = pack_rows(lo >> 8, hi >> 8);
+            if constexpr (CLAMP) {
+                if constexpr (MODE == MODE_GEODESIC) {
+                    const uint32_t mlo = *reinterpret_cast<const uint16_t *>(msk + base + j * a.pitch);
+                    const uint32_t mhi = *reinterpret_cast<const uint16_t *>(msk + base + (j + H) * a.pitch);
+                    m[j][0] = pack_rows(mlo & 0xFFu, mhi & 0xFFu);
+                    m[j][1] = pack_rows(mlo >> 8, mhi >> 8);
+                } else {
+                    m[j][0] = m[j][1] = pack_rows(B::top(), B::top());
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                const int x = rx0 + lane * CW + c;
+                const bool xin = (unsigned)x < (unsigned)a.width;
+                uint32_t vv[2], mm[2];
+#pragma unroll
+                for (int half = 0; half < 2; ++half) {
+                    const int y = ry0 + w * RPW + j + half * H;
+                    const bool in = xin && (unsigned)y < (unsigned)a.height;
+                    const int64_t off = (int64_t)y * a.pitch + x;
+                    vv[half] = in ? (uint32_t)src[off] : B::bottom();
+                    if constexpr (MODE == MODE_GEODESIC)
+                        mm[half] = in ? (uint32_t)msk[off] : B::bottom();
+                    else
+                        mm[half] = in ? B::top() : B::bottom();
+                }
+                v[j][c] = pack_rows(vv[0], vv[1]);
+                if constexpr (CLAMP) m[j][c] = pack_rows(mm[0], mm[1]);
+            }
+        }
+    }
+
+    uint64_t col_in_core[CW];
+    if constexpr (DETECT) {
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+            const int cx = lane * CW + c;
+            const int x = rx0 + cx;
+            const bool ok = cx >= halo && cx < halo + a.core_x && x < a.width;
+            col_in_core[c] = __builtin_amdgcn_ballot_w64(ok);
+        }
+    }
+    uint32_t step_bits = 0;
+
+    const int busy_a = w * RPW + RPW - (halo - k);
+    const int busy_b = halo + a.core_y + k - w * RPW;
+    const int busy = __builtin_amdgcn_readfirstlane(max(0, min(k, min(busy_a, busy_b))));
+    const bool wave_has_core = DETECT && w * RPW + RPW > halo && w * RPW < halo + a.core_y;
+
+    auto run_steps = [&](auto detect_tag) {
+        constexpr bool D = decltype(detect_tag)::value;
+        if (busy == 0) return;
+        uint32_t h[H][CW];
+        uint32_t above[CW], below[CW];
+        const int wa = w > 0 ? w - 1 : NW - 1;
+        const int wb = w < NW - 1 ? w + 1 : 0;
+        auto row_pass = [&](int j) {
+            const uint32_t left = lane_shift<DPP_WAVE_SHR1>(v[j][1]);
+            const uint32_t right = lane_shift<DPP_WAVE_SHL1>(v[j][0]);
+            const uint32_t t = P::pick(v[j][0], v[j][1]);
+            h[j][0] = P::pick(t, left);
+            h[j][1] = P::pick(t, right);
+        };
+        auto publish = [&](int par) {
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                xch[par][w][0][lane * CW + c] = h[0][c];
+                xch[par][w][1][lane * CW + c] = h[H - 1][c];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                above[c] = xch[par][wa][1][lane * CW + c];
+                below[c] = xch[par][wb][0][lane * CW + c];
+            }
+        };
+        // 16-bit row masks of the core for register j (low and high rows)
+        auto core_mask = [&](int j) {
+            const int ry = w * RPW + j;
+            const bool lo = ry >= halo && ry < halo + a.core_y && ry0 + ry < a.height;
+            const bool hi = ry + H >= halo && ry + H < halo + a.core_y && ry0 + ry + H < a.height;
+            return (lo ? 0x0000FFFFu : 0u) | (hi ? 0xFFFF0000u : 0u);
+        };
+        auto finish = [&](int j, int c, uint32_t x, uint32_t (&nv)[H][CW], uint64_t &changed) {
+            if constexpr (CLAMP) x = P::clamp(x, m[j][c]);
+            if constexpr (D) changed |= __builtin_amdgcn_ballot_w64(((x ^ v[j][c]) & core_mask(j)) != 0) &
+                                        col_in_core[c];
+            nv[j][c] = x;
+        };
+
+#pragma unroll
+        for (int j = 0; j < H; ++j) row_pass(j);
+        publish(0);
+        for (int s = 0; s < busy; ++s) {
+            uint32_t nv[H][CW];
+            uint64_t changed = 0;
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                // middle registers: pairs share their extremum
+#pragma unroll
+                for (int j = 1; j < H - 1; ++j) {
+                    const uint32_t up = h[j - 1][c], dn = h[j + 1][c];
+                    finish(j, c, P::pick(P::pick(up, h[j][c]), dn), nv, changed);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                // seams: rows above register 0 are (wave above's last row,
+                // this wave's row H - 1); rows below register H - 1 are
+                // (this wave's row H, wave below's first row)
+                const uint32_t up0 = __builtin_amdgcn_alignbit(h[H - 1][c], above[c], 16);
+                const uint32_t dnl = __builtin_amdgcn_alignbit(below[c], h[0][c], 16);
+                if constexpr (H == 1) {
+                    finish(0, c, P::pick(P::pick(up0, h[0][c]), dnl), nv, changed);
+                } else {
+                    finish(0, c, P::pick(P::pick(up0, h[0][c]), h[1][c]), nv, changed);
+                    finish(H - 1, c, P::pick(P::pick(h[H - 2][c], h[H - 1][c]), dnl), nv, changed);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < H; ++j)
+#pragma unroll
+                for (int c = 0; c < CW; ++c) v[j][c] = nv[j][c];
+            if constexpr (D) {
+                if (changed) step_bits |= 1u << s;
+            }
+            if (s + 1 < busy) {
+                row_pass(0);
+                if constexpr (H > 1) row_pass(H - 1);
+                publish((s + 1) & 1);
+#pragma unroll
+                for (int j = 1; j < H - 1; ++j) row_pass(j);
+            }
+        }
+    };
+    if (wave_has_core)
+        run_steps(std::true_type{});
+    else
+        run_steps(std::false_type{});
+    for (int s = busy; s < k; ++s) __syncthreads();
+
+    // ---- store the core ----
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        const int ry = w * RPW + r;
+        const int y = ry0 + ry;
+        const bool yok = ry >= halo && ry < halo + a.core_y && y < a.height;
+        if (!yok) continue;
+        const int j = r < H ? r : r - H;
+        const int sh = r < H ? 0 : 16;
+        const uint32_t c0 = (v[j][0] >> sh) & 0xFFu, c1 = (v[j][1] >> sh) & 0xFFu;
+        const int cx = lane * 2;
+        const int x = rx0 + cx;
+        uint8_t *p = dst + (int64_t)y * a.pitch + x;
+        const bool in0 = cx >= halo && cx < halo + a.core_x && x < a.width;
+        const bool in1 = cx + 1 >= halo && cx + 1 < halo + a.core_x && x + 1 < a.width;
+        if (in0 && in1 && (fast || pair_aligned(p))) {
+            *reinterpret_cast<uint16_t *>(p) = (uint16_t)(c0 | (c1 << 8));
+        } else {
+            if (in0) *p = (uint8_t)c0;
+            if (in1) p[1] = (uint8_t)c1;
+        }
+    }
+    return step_bits;
+}
+
 template <int G> constexpr int lanes_per_group() { return 64 / G; }
 
 // Plain chains skip the border fence for regions entirely inside the image.
@@ -607,6 +846,15 @@ __device__ __forceinline__ uint32_t chain_block_dispatch(
             return chain_block_body_g2<T, OP, MODE, true, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
         } else {
             return chain_block_body_g2<T, OP, MODE, true, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
+        }
+    } else if constexpr (std::is_same<T, uint8_t>::value && CW == 2 && RPW % 2 == 0) {
+        // u8: two rows per register, packed 16-bit max/min
+        if constexpr (MODE == MODE_PLAIN) {
+            const bool inside = rx0 >= 0 && ry0 >= 0 && rx0 + RX <= a.width && ry0 + RY <= a.height;
+            if (inside) return chain_block_body_pk<OP, MODE, false, DETECT, RPW, NW>(a, rx0, ry0, xch);
+            return chain_block_body_pk<OP, MODE, true, DETECT, RPW, NW>(a, rx0, ry0, xch);
+        } else {
+            return chain_block_body_pk<OP, MODE, true, DETECT, RPW, NW>(a, rx0, ry0, xch);
         }
     } else if constexpr (MODE == MODE_PLAIN) {
         const bool inside = rx0 >= 0 && ry0 >= 0 && rx0 + RX <= a.width && ry0 + RY <= a.height;
