@@ -247,6 +247,14 @@ int gc_quasi_distance(gc_dtype dtype, const void *f, int32_t *dist, void *residu
  * gc_plan_info reports totals of the plan (any pointer may be NULL):
  * pixel-steps per launch, work items, workgroups launched, tile family and
  * the largest steps-per-block used.
+ *
+ * gc_plan_tune times the kernel's launch shapes (tile family x steps per
+ * block, the built-in choice among them) on scratch images with exactly
+ * this plan's shapes and chain lengths -- the caller's images are not read
+ * or written, so in-place items are safe -- and rebuilds the plan with the
+ * fastest.  The handle stays valid; *best_ms (host, may be NULL) receives
+ * the winner's time per launch.  Synchronises; allocates scratch for three
+ * images per item while it runs.
  * ------------------------------------------------------------------- */
 typedef struct {
     const void *marker;
@@ -265,6 +273,7 @@ int gc_plan_status(gc_plan *plan);
 int gc_plan_info(const gc_plan *plan, int64_t *px_steps, int64_t *work_items,
                  int32_t *workgroups, int32_t *tile, int32_t *block_steps);
 int gc_plan_destroy(gc_plan *plan);
+int gc_plan_tune(gc_plan *plan, double *best_ms);
 
 /* ---------------------------------------------------------------------
  * Autotuner.  Times every candidate (tile family x steps per block) of the

@@ -72,6 +72,7 @@ SIGNATURES = {
     "gc_plan_info": (ctypes.c_int, [_VP, _P_I64, _P_I64, ctypes.POINTER(_I32),
                                     ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "gc_plan_destroy": (ctypes.c_int, [_VP]),
+    "gc_plan_tune": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double)]),
     "gc_autotune": (ctypes.c_int, [_DT, _DT, _I32, _I64, _I64, ctypes.POINTER(_I32),
                                    ctypes.POINTER(_I32)]),
     "gc_autotune_clear": (ctypes.c_int, []),

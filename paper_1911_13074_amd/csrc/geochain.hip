@@ -1848,6 +1848,79 @@ int gc_plan_create(gc_dtype dtype, gc_op op, const gc_item *items, int32_t n_ite
     return plan_build(dtype, (int)op, items, n_items, plan_out, nullptr);
 }
 
+int gc_plan_tune(gc_plan *plan, double *best_ms) {
+    g_last_error.clear();
+    if (!plan) return fail(GC_ERR_INVALID_ARG, "plan is NULL");
+    int dev = 0;
+    GC_HIP(hipGetDevice(&dev));
+    if (dev != plan->device) return fail(GC_ERR_INVALID_ARG, "plan belongs to device %d", plan->device);
+    if (plan->launched) GC_HIP(hipStreamSynchronize(plan->last_stream));
+    const size_t es = elem_size(plan->dtype);
+    const size_t n = plan->items.size();
+    // Scratch images of the same shapes and chain lengths: the kernels'
+    // cost does not depend on the pixel values, and the caller's buffers
+    // (in-place items included) are never touched.
+    std::vector<size_t> off(n);
+    size_t total = 0;
+    for (size_t i = 0; i < n; ++i) {
+        const gc_shape &sh = plan->items[i].shape;
+        off[i] = total;
+        total += 3 * (((size_t)(sh.width * sh.height) * es + 255) & ~(size_t)255);
+    }
+    void *buf = nullptr;
+    if (total && hipMalloc(&buf, total) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GC_ERR_NO_MEMORY, "tuning scratch of %zu bytes", total);
+    }
+    if (total) GC_HIP(hipMemset(buf, 0, total));
+    std::vector<gc_item> scratch(n);
+    for (size_t i = 0; i < n; ++i) {
+        const gc_item &it = plan->items[i];
+        const size_t plane = ((size_t)(it.shape.width * it.shape.height) * es + 255) & ~(size_t)255;
+        char *b = static_cast<char *>(buf) + off[i];
+        scratch[i].marker = b;
+        scratch[i].mask = it.mask ? b + plane : nullptr;
+        scratch[i].out = b + 2 * plane;
+        scratch[i].shape = gc_shape{it.shape.width, it.shape.height, it.shape.width};
+        scratch[i].n_steps = it.n_steps;
+    }
+    PlanChoice best;
+    double best_t = 1e300;
+    const int fams[] = {FAM_128W, FAM_128, FAM_96W, FAM_96};
+    for (int fam : fams) {
+        for (int k = 12; k <= std::min(28, persistent_kmax(fam)); k += 4) {
+            PlanChoice ch;
+            ch.fam = fam;
+            for (size_t i = 0; i < n; ++i) {
+                const int64_t ni = plan->items[i].n_steps;
+                ch.k.push_back(ni > 0 && ni < k ? (int)ni : k);
+            }
+            gc_plan *cand = nullptr;
+            if (plan_build(plan->dtype, plan->op, scratch.data(), (int32_t)n, &cand, &ch) != GC_OK) continue;
+            double ms = 0;
+            const int rc = plan_time(cand, 2, &ms);
+            plan_free(cand);
+            if (rc != GC_OK) {
+                if (buf) (void)hipFree(buf);
+                return rc;
+            }
+            if (ms < best_t) {
+                best_t = ms;
+                best = ch;
+            }
+        }
+    }
+    if (buf) (void)hipFree(buf);
+    if (best_t == 1e300) return fail(GC_ERR_UNSUPPORTED, "no launch shape could be built for this batch");
+    gc_plan *tuned = nullptr;
+    int rc = plan_build(plan->dtype, plan->op, plan->items.data(), (int32_t)n, &tuned, &best);
+    if (rc != GC_OK) return rc;
+    std::swap(*plan, *tuned);   // the caller's handle now holds the tuned plan
+    plan_free(tuned);
+    if (best_ms) *best_ms = best_t;
+    return GC_OK;
+}
+
 int gc_plan_launch(gc_plan *plan, void *hip_stream) {
     g_last_error.clear();
     if (!plan) return fail(GC_ERR_INVALID_ARG, "plan is NULL");

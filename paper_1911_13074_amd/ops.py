@@ -295,6 +295,16 @@ class BatchPlan:
         return {"px_steps": px.value, "work_items": items.value, "workgroups": wgs.value,
                 "tile": tile.value, "block_steps": k.value}
 
+    def tune(self):
+        """Time the launch shapes on scratch images of this batch's shapes
+        and rebuild the plan with the fastest; returns its ms per launch."""
+        ms = ctypes.c_double()
+        dev = self.device if self.device is not None else torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(dev):
+            torch.cuda.current_stream(dev).synchronize()
+            abi.check(abi.gc_plan_tune(self._plan, ctypes.byref(ms)), "gc_plan_tune")
+        return ms.value
+
     def close(self):
         if self._plan is not None:
             abi.gc_plan_destroy(self._plan)

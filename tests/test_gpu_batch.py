@@ -162,3 +162,36 @@ def test_uneven_batch_workload_sampled():
     for i, it in enumerate(batch.items):
         o = plan.outs[i]
         assert torch.all(o >= dev_items[i][0]) and torch.all(o <= dev_items[i][1]), f"bounds {i}"
+
+
+def test_tuned_plan_matches_and_leaves_inputs_alone():
+    """gc_plan_tune times launch shapes on scratch images, then rebuilds the
+    plan: results stay bit-exact, in-place items keep their input until the
+    launch, and the tuned plan is never slower than the built-in by more
+    than noise."""
+    rng = np.random.default_rng(21)
+    shapes = [(300, 517), (128, 128), (1, 700), (700, 1), (257, 199)]
+    items, refs, keep = [], [], []
+    for i, (h, w) in enumerate(shapes):
+        m = rng.integers(0, 256, size=(h, w)).astype(np.uint8)
+        f = np.minimum(m, rng.integers(0, 256, size=(h, w)).astype(np.uint8))
+        n = int(rng.integers(5, 90))
+        F, M = torch.from_numpy(f).cuda(), torch.from_numpy(m).cuda()
+        if i == 0:
+            items.append((F, M, n, F))      # in place
+        else:
+            items.append((F, M, n))
+        keep.append((F, M))
+        refs.append(oracle.chain(oracle.DILATE, f, n, m))
+    plan = gc.BatchPlan("dilate", items)
+    before = keep[0][0].clone()
+    ms = plan.tune()
+    assert ms > 0
+    assert torch.equal(keep[0][0], before)   # tuning never touched the caller's images
+    outs = plan.launch()
+    plan.status()
+    info = plan.info()
+    assert info["tile"] in (0, 2, 3, 4) and 1 <= info["block_steps"] <= 28
+    for out, ref in zip(outs, refs):
+        assert np.array_equal(out.cpu().numpy(), ref)
+    plan.close()
