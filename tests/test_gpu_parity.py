@@ -289,3 +289,42 @@ def test_image_beyond_2_31_pixels_sampled():
         assert int(out[y, x]) == int(ref), (y, x)
     del F, M, out
     torch.cuda.empty_cache()
+
+
+# --------------------------------------------------------------------------
+# seeded random sweep over shapes, pitches, dtypes, modes and chain lengths
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("case", range(40))
+def test_random_configurations(case):
+    rng = np.random.default_rng(1000 + case)
+    dtype = [np.uint8, np.float32, np.float64][int(rng.integers(0, 3))]
+    op = int(rng.integers(0, 2))
+    geodesic = bool(rng.integers(0, 2))
+    h, w = int(rng.integers(1, 700)), int(rng.integers(1, 700))
+    pad = int(rng.integers(0, 3)) * int(rng.integers(1, 40))
+    n = int(rng.choice([0, 1, 2, int(rng.integers(3, 40)), int(rng.integers(40, 151))]))
+    in_place = bool(rng.integers(0, 2))
+    f, m = rand_pair((h, w), dtype, seed=case, levels=int(rng.choice([3, 8, 256])))
+    tdt = dev(f).dtype
+    F = torch.zeros((h, w + pad), dtype=tdt, device="cuda")
+    F[:, :w] = dev(f)
+    M = torch.zeros_like(F)
+    M[:, :w] = dev(m)
+    fv, mv = F[:, :w], M[:, :w]
+    what = f"case {case}: {np.dtype(dtype)} op={op} geodesic={geodesic} {h}x{w}+{pad} n={n} in_place={in_place}"
+    out = fv if in_place else None
+    if geodesic:
+        fn = gc.geodesic_dilate_chain if op == oracle.DILATE else gc.geodesic_erode_chain
+        got = fn(fv, mv, n, out=out)
+        ref = oracle.chain(op, f, n, m)
+    else:
+        fn = gc.dilate_chain if op == oracle.DILATE else gc.erode_chain
+        got = fn(fv, n, out=out)
+        ref = oracle.chain(op, f, n)
+    assert_same(host(got), ref, what)
+    if geodesic and n % 3 == 0 and h * w <= 200 * 700:
+        rfn = gc.reconstruct_by_dilation if op == oracle.DILATE else gc.reconstruct_by_erosion
+        r, steps, conv = rfn(dev(f), dev(m))
+        rref, rsteps, rconv = oracle.reconstruct(op, f, m)
+        assert conv and rconv and steps == rsteps, what
+        assert_same(host(r), rref, what + " reconstruction")
