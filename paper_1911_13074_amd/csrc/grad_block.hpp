@@ -15,27 +15,28 @@
 // q, visiting p in raster order (the order a raster-order scatter delivers
 // them), and the mask gradient collects g(q) where code(q) == 9.
 //
-// Both kernels are temporal-blocked: up to GB_K steps per launch on a 64 x 64
-// tile with a GB_K-pixel halo held in LDS.
+// Both kernels are temporal-blocked: up to GB_K steps per launch on a region
+// of 64 columns (one per lane) and NW * 8 rows with a GB_K-pixel halo.  Each
+// wave keeps its 8 rows in registers; the left and right columns come from
+// the adjacent lanes by DPP and only the wave's two edge rows go through
+// LDS, one barrier per step.  A wave whose rows are all further than the
+// remaining steps from the core only takes the barriers.
 //
-//   block_codes_kernel  k steps forward; codes of the core pixels are staged
-//                       in LDS and stored as 16-byte rows;
-//   block_bwd_kernel    k steps backward; the mask gradient is accumulated in
-//                       registers starting from the stored value, so its
-//                       additions happen in the same order (steps from last to
-//                       first) as in a one-step-at-a-time reverse pass.
+//   block_codes_kernel  k steps forward; the codes of the core pixels are
+//                       staged in LDS and stored as 16-byte rows;
+//   block_bwd_kernel    k steps backward with the k code planes in LDS; the
+//                       mask gradient is accumulated in registers starting
+//                       from the stored value, so its additions happen in the
+//                       same order (steps from last to first) as in a
+//                       one-step-at-a-time reverse pass.
 //
 // Values must be finite: a pixel outside the image is represented by the
 // neutral extremum (-inf for dilation), which must never tie with a real
 // value.  Codes are stored densely: codes[image][step][y][width] bytes.
-//
-// Layout: lane = region column (64 per region), wave w = region rows
-// [8w, 8w + 8).  Each lane walks its 8 rows keeping the row-pass results (or
-// codes and gradients) of three rows on a rolling window; the left and right
-// columns come from the adjacent lanes by DPP, so a step costs one LDS read
-// per pixel and array.  After step s of k only the band
-// within k-1-s of the core is still needed; waves outside it skip.  One
-// launch covers a batch of images (grid.z = image).
+// Pixels on the region's outer edge (lanes 0 and 63, the first and last
+// wave's outer rows) see wrong neighbours; an error moves one pixel per step
+// and the core starts GB_K pixels in, so the core is exact.  One launch
+// covers a batch of images (grid.z = image).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -121,13 +122,33 @@ __device__ __forceinline__ void gb_store_codes(const uint8_t (*sc)[GB_CX], uint8
     }
 }
 
+// Rows a wave must still compute at step s of a k-step launch: those whose
+// result is needed (within k-1-s of the core) and, one further out, those
+// whose row-pass result or gradient a needed edge row reads from this wave.
+// A wave holding any of them computes all of its rows; the others only take
+// the barriers: what they leave stale lies at least k-s rows from the core
+// and moves at most one row per remaining step, so it never reaches it.
+template <int CY>
+__device__ __forceinline__ bool gb_wave_busy(int w, int k, int s) {
+    const int lo = GB_K - (k - s), hi = GB_K + CY + (k - s);
+    return w * GB_WR + GB_WR > lo && w * GB_WR < hi;
+}
+
+// Forward: k steps of the chain recording every core pixel's source code.
+// Each wave keeps its GB_WR rows of the state in registers (lane = column);
+// the row pass takes the neighbour columns by DPP, the column pass reads the
+// rows above and below from the wave's own registers, and only the two edge
+// rows' row-pass results (value and index) go through LDS, one barrier per
+// step.  The codes of a step are staged in LDS (double-buffered) and stored
+// as 16-byte rows after the next step's barrier.
 template <typename T, int OP>
 __global__ __launch_bounds__(GradTile<T>::THREADS) void block_codes_kernel(GradBlockArgs a) {
     using B = Bounds<T, OP>;
     using G = GradTile<T>;
-    constexpr int RH = G::RH, CY = G::CY;
-    __shared__ T sf[2][RH][GB_RW];
-    __shared__ __attribute__((aligned(16))) uint8_t sc[CY][GB_CX];
+    constexpr int CY = G::CY, NW = G::NW;
+    __shared__ T xv[2][NW][2][GB_RW];        // edge rows' row-pass values
+    __shared__ uint8_t xi[2][NW][2][GB_RW];  // and their dx indices
+    __shared__ __attribute__((aligned(16))) uint8_t sc[2][CY][GB_CX];
     const int img = blockIdx.z;
     const T *src = static_cast<const T *>(a.src) + img * a.image_stride;
     const T *msk = static_cast<const T *>(a.mask) + img * a.image_stride;
@@ -137,79 +158,93 @@ __global__ __launch_bounds__(GradTile<T>::THREADS) void block_codes_kernel(GradB
     const int rx0 = x0 - GB_K, ry0 = y0 - GB_K;               // region origin
     const int x = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wa = w > 0 ? w - 1 : NW - 1, wb = w < NW - 1 ? w + 1 : 0;  // region edge: harmless wrap
     const int gx = rx0 + x;
     const bool xin = (unsigned)gx < (unsigned)a.width;
+    const bool col_core = (unsigned)(x - GB_K) < (unsigned)GB_CX;
 
-    // state plane 0 and the lane's mask rows
-    T m[GB_WR];
+    T v[GB_WR], m[GB_WR];
 #pragma unroll
     for (int r = 0; r < GB_WR; ++r) {
-        const int ly = w * GB_WR + r, y = ry0 + ly;
+        const int y = ry0 + w * GB_WR + r;
         const bool in = xin && (unsigned)y < (unsigned)a.height;
         const int64_t off = (int64_t)y * a.pitch + gx;
-        sf[0][ly][x] = in ? src[off] : B::bottom();
+        v[r] = in ? src[off] : B::bottom();
         m[r] = in ? msk[off] : B::bottom();
     }
-    __syncthreads();
 
     const int k = a.k;
-    int cur = 0;
     for (int s = 0; s < k; ++s) {
-        const int lo = GB_K - (k - 1 - s), hi_r = GB_K + CY + (k - 1 - s);  // rows needed after this step
-        // A wave with any needed row computes all its rows: the others are
-        // never read again (their window rows are clamped into the tile).
-        if (w * GB_WR + GB_WR > lo && w * GB_WR < hi_r) {
-            // row pass (value, dx index) of rows y-1, y, y+1 on a rolling window
-            auto row_pass = [&](int ly, T &v, int &ix) {
-                const T c = sf[cur][ly][x];
-                v = gb_shift<DPP_WAVE_SHR1>(c);
-                const T r = gb_shift<DPP_WAVE_SHL1>(c);
-                ix = 0;
-                if (better<OP>(c, v)) { v = c; ix = 1; }
-                if (better<OP>(r, v)) { v = r; ix = 2; }
-            };
-            T h0, h1, h2;
-            int i0, i1, i2;
-            row_pass(max(w * GB_WR - 1, 0), h0, i0);
-            row_pass(w * GB_WR, h1, i1);
+        const int par = s & 1;
+        const bool busy = gb_wave_busy<CY>(w, k, s);
+        T h[GB_WR];
+        int ix[GB_WR];
+        if (busy) {
+            // row pass: first extremum of (x-1, x, x+1) and its dx index
 #pragma unroll
             for (int r = 0; r < GB_WR; ++r) {
-                const int y = w * GB_WR + r;
-                row_pass(min(y + 1, RH - 1), h2, i2);
-                T best = h0;
-                int code = i0;
-                if (better<OP>(h1, best)) { best = h1; code = 3 + i1; }
-                if (better<OP>(h2, best)) { best = h2; code = 6 + i2; }
-                const bool mask_wins = OP == OP_DILATE ? !(best < m[r]) : !(best > m[r]);
-                sf[cur ^ 1][y][x] = mask_wins ? m[r] : best;
-                const int cy = y - GB_K, cx = x - GB_K;
-                if ((unsigned)cy < (unsigned)CY && (unsigned)cx < (unsigned)GB_CX)
-                    sc[cy][cx] = mask_wins ? CODE_MASK : (uint8_t)code;
-                h0 = h1; i0 = i1;
-                h1 = h2; i1 = i2;
+                const T c = v[r];
+                T best = gb_shift<DPP_WAVE_SHR1>(c);
+                const T right = gb_shift<DPP_WAVE_SHL1>(c);
+                int i = 0;
+                if (better<OP>(c, best)) { best = c; i = 1; }
+                if (better<OP>(right, best)) { best = right; i = 2; }
+                h[r] = best;
+                ix[r] = i;
             }
+            xv[par][w][0][x] = h[0];
+            xi[par][w][0][x] = (uint8_t)ix[0];
+            xv[par][w][1][x] = h[GB_WR - 1];
+            xi[par][w][1][x] = (uint8_t)ix[GB_WR - 1];
         }
         __syncthreads();
-        gb_store_codes<CY>(sc, codes + s * a.codes_step, x0, y0, a.width, a.height);
-        cur ^= 1;
-        __syncthreads();
+        // the previous step's codes are complete: store them
+        if (s > 0) gb_store_codes<CY>(sc[par ^ 1], codes + (s - 1) * a.codes_step, x0, y0, a.width, a.height);
+        if (busy) {
+            const T ha = xv[par][wa][1][x], hb = xv[par][wb][0][x];
+            const int ia = xi[par][wa][1][x], ib = xi[par][wb][0][x];
+            // column pass: first extremum of rows y-1, y, y+1 in raster order,
+            // then the clamp (the mask wins ties)
+#pragma unroll
+            for (int r = 0; r < GB_WR; ++r) {
+                T best = r == 0 ? ha : h[r - 1];
+                int code = r == 0 ? ia : ix[r - 1];
+                if (better<OP>(h[r], best)) { best = h[r]; code = 3 + ix[r]; }
+                const T hd = r == GB_WR - 1 ? hb : h[r + 1];
+                const int id = r == GB_WR - 1 ? ib : ix[r + 1];
+                if (better<OP>(hd, best)) { best = hd; code = 6 + id; }
+                const bool mask_wins = OP == OP_DILATE ? !(best < m[r]) : !(best > m[r]);
+                v[r] = mask_wins ? m[r] : best;
+                const int cy = w * GB_WR + r - GB_K;
+                if ((unsigned)cy < (unsigned)CY && col_core)
+                    sc[par][cy][x - GB_K] = mask_wins ? CODE_MASK : (uint8_t)code;
+            }
+        }
     }
+    __syncthreads();
+    gb_store_codes<CY>(sc[(k - 1) & 1], codes + (k - 1) * a.codes_step, x0, y0, a.width, a.height);
     // core of the final state
-    if ((unsigned)(x - GB_K) < (unsigned)GB_CX && xin) {
+    if (col_core && xin) {
 #pragma unroll
         for (int r = 0; r < GB_WR; ++r) {
             const int ly = w * GB_WR + r, y = ry0 + ly;
-            if ((unsigned)(ly - GB_K) < (unsigned)CY && y < a.height) dst[(int64_t)y * a.pitch + gx] = sf[cur][ly][x];
+            if ((unsigned)(ly - GB_K) < (unsigned)CY && y < a.height) dst[(int64_t)y * a.pitch + gx] = v[r];
         }
     }
 }
 
+// Backward: k steps of the reverse gather.  Each wave keeps its rows'
+// gradients in registers; the codes of the k steps sit in LDS; the two edge
+// rows' gradients go through LDS each step.  Pixel q takes, in raster
+// order, the upstream gradient of each neighbour p = q + d whose code names
+// -d, and adds its own gradient to the mask gradient where its code is
+// CODE_MASK.
 template <typename T>
 __global__ __launch_bounds__(GradTile<T>::THREADS) void block_bwd_kernel(GradBlockArgs a) {
     using G = GradTile<T>;
-    constexpr int RH = G::RH, CY = G::CY;
-    __shared__ T sg[2][RH][GB_RW];
+    constexpr int RH = G::RH, CY = G::CY, NW = G::NW;
     __shared__ __attribute__((aligned(16))) uint8_t scd[GB_K][RH][GB_RW];
+    __shared__ T xg[2][NW][2][GB_RW];
     const int img = blockIdx.z;
     const T *gin = static_cast<const T *>(a.src) + img * a.image_stride;
     T *gout = static_cast<T *>(a.dst) + img * a.image_stride;
@@ -219,18 +254,20 @@ __global__ __launch_bounds__(GradTile<T>::THREADS) void block_bwd_kernel(GradBlo
     const int rx0 = x0 - GB_K, ry0 = y0 - GB_K;
     const int x = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wa = w > 0 ? w - 1 : NW - 1, wb = w < NW - 1 ? w + 1 : 0;
     const int gx = rx0 + x;
     const bool xin = (unsigned)gx < (unsigned)a.width;
     const int k = a.k;
 
-    // gradient plane 0; codes of the k steps (words where the region is
-    // inside the image and aligned, else bytes)
+    T g[GB_WR];
 #pragma unroll
     for (int r = 0; r < GB_WR; ++r) {
-        const int ly = w * GB_WR + r, y = ry0 + ly;
+        const int y = ry0 + w * GB_WR + r;
         const bool in = xin && (unsigned)y < (unsigned)a.height;
-        sg[0][ly][x] = in ? gin[(int64_t)y * a.pitch + gx] : T(0);
+        g[r] = in ? gin[(int64_t)y * a.pitch + gx] : T(0);
     }
+    // codes of the k steps (words where the region is inside the image and
+    // aligned, else bytes; outside the image: CODE_NONE)
     const bool inside = rx0 >= 0 && ry0 >= 0 && rx0 + GB_RW <= a.width && ry0 + RH <= a.height &&
                         (a.width & 3) == 0 && (((uintptr_t)codes + rx0) & 3) == 0 && (a.codes_step & 3) == 0;
     if (inside) {
@@ -262,31 +299,42 @@ __global__ __launch_bounds__(GradTile<T>::THREADS) void block_bwd_kernel(GradBlo
     }
     __syncthreads();
 
-    int cur = 0;
     for (int s = k - 1; s >= 0; --s) {
-        const int lo = GB_K - s, hi_r = GB_K + CY + s;  // rows needed after this step
-        // As in the forward kernel: all rows of a wave or none.
-        if (w * GB_WR + GB_WR > lo && w * GB_WR < hi_r) {
-            // rolling window of (code, gradient) at columns x-1, x, x+1 of
-            // rows y-1, y, y+1
-            auto load_row = [&](int ly, int *c, T *g) {
+        const int par = s & 1;
+        // as forward: rows within s of the core still matter
+        const bool busy = gb_wave_busy<CY>(w, k, k - 1 - s);
+        if (busy) {
+            xg[par][w][0][x] = g[0];
+            xg[par][w][1][x] = g[GB_WR - 1];
+        }
+        __syncthreads();
+        if (busy) {
+            const T ga = xg[par][wa][1][x], gb = xg[par][wb][0][x];
+            const int base = w * GB_WR;
+            // codes and gradients of the rows around row r, columns x-1, x, x+1
+            auto code_row = [&](int ly, int *c) {
                 c[1] = scd[s][ly][x];
-                g[1] = sg[cur][ly][x];
                 c[0] = gb_shift<DPP_WAVE_SHR1>(c[1]);
-                g[0] = gb_shift<DPP_WAVE_SHR1>(g[1]);
                 c[2] = gb_shift<DPP_WAVE_SHL1>(c[1]);
-                g[2] = gb_shift<DPP_WAVE_SHL1>(g[1]);
+            };
+            auto grad_row = [&](T gc, T *gr) {
+                gr[1] = gc;
+                gr[0] = gb_shift<DPP_WAVE_SHR1>(gc);
+                gr[2] = gb_shift<DPP_WAVE_SHL1>(gc);
             };
             int c0[3], c1[3], c2[3];
             T g0[3], g1[3], g2[3];
-            load_row(max(w * GB_WR - 1, 0), c0, g0);
-            load_row(w * GB_WR, c1, g1);
+            code_row(base > 0 ? base - 1 : RH - 1, c0);
+            grad_row(ga, g0);
+            code_row(base, c1);
+            grad_row(g[0], g1);
+            T ng[GB_WR];
 #pragma unroll
             for (int r = 0; r < GB_WR; ++r) {
-                const int y = w * GB_WR + r;
-                load_row(min(y + 1, RH - 1), c2, g2);
-                // neighbour p = q + d, d in raster order j; it sent to q iff
-                // its code is 8 - j
+                code_row(base + r + 1 < RH ? base + r + 1 : 0, c2);
+                grad_row(r == GB_WR - 1 ? gb : g[r + 1], g2);
+                // neighbour p = q + d, d in raster order j, sent to q iff its
+                // code is 8 - j
                 T sum = T(0);
 #pragma unroll
                 for (int d = 0; d < 3; ++d)
@@ -297,7 +345,7 @@ __global__ __launch_bounds__(GradTile<T>::THREADS) void block_bwd_kernel(GradBlo
 #pragma unroll
                 for (int d = 0; d < 3; ++d)
                     if (c2[d] == 2 - d) sum += g2[d];
-                sg[cur ^ 1][y][x] = sum;
+                ng[r] = sum;
                 if (c1[1] == CODE_MASK) acc[r] += g1[1];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
@@ -305,16 +353,16 @@ __global__ __launch_bounds__(GradTile<T>::THREADS) void block_bwd_kernel(GradBlo
                     c1[d] = c2[d]; g1[d] = g2[d];
                 }
             }
+#pragma unroll
+            for (int r = 0; r < GB_WR; ++r) g[r] = ng[r];
         }
-        cur ^= 1;
-        __syncthreads();
     }
     // gradient w.r.t. the state before the block, and the mask gradient
 #pragma unroll
     for (int r = 0; r < GB_WR; ++r) {
         const int ly = w * GB_WR + r, y = ry0 + ly;
         if (col_core && (unsigned)(ly - GB_K) < (unsigned)CY && y < a.height) {
-            gout[(int64_t)y * a.pitch + gx] = sg[cur][ly][x];
+            gout[(int64_t)y * a.pitch + gx] = g[r];
             gm[(int64_t)y * a.pitch + gx] = acc[r];
         }
     }
