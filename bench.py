@@ -29,8 +29,10 @@ import torch  # noqa: E402
 import workloads  # noqa: E402
 
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes = 64 VALU lane-ops per clock per CU at
-# 2.4 GHz; v_max3 / v_min3 perform two compare-selects per lane-op.
-PEAK_TCMP = 256 * 64 * 2.4e9 * 2 / 1e12   # 78.64 T compare-selects / s
+# 2.4 GHz.  The densest compare-select instruction, the packed three-input
+# half-precision maximum/minimum (exact for 8-bit values), performs four
+# compare-selects per lane-op at full rate.
+PEAK_TCMP = 256 * 64 * 2.4e9 * 4 / 1e12   # 157.29 T compare-selects / s
 CMP_PER_PX_STEP_GEODESIC = 5
 CMP_PER_PX_STEP_PLAIN = 4
 

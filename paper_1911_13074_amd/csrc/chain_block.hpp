@@ -591,43 +591,60 @@ __device__ __forceinline__ uint32_t chain_block_body_g2(const BlockArgs &a, int 
     return step_bits;
 }
 
-// Lanes per column group: 64 (one group) or 32 (two groups).
 // ---------------------------------------------------------------------------
 // u8 body with two rows per register.  Register row j of a wave holds its
 // region rows j (low 16 bits) and j + RPW/2 (high 16 bits), so each packed
-// 16-bit max/min handles two pixels; both rows belong to the same wave, so
-// the busy band, the edge exchange and the row pass are those of
+// instruction handles two pixels; both rows belong to the same wave, so the
+// busy band, the edge exchange and the row pass are those of
 // chain_block_body.  The column pass meets the halves' seams twice: the row
 // above register 0's low half is the wave above's last row (the high half of
 // its last register) and the row above its high half is this wave's
 // register RPW/2 - 1, low half; one funnel shift (alignbit) builds each seam
-// operand, and likewise below the last register.  Pixel values stay in
-// 0..255, so every 16-bit lane holds an exact u8 value.
+// operand, and likewise below the last register.
+//
+// A pixel value p in 0..255 is held as the half-precision number 1024 + p,
+// whose bit pattern is 0x6400 | p (binary16 has unit spacing on
+// [1024, 2048)).  Encoding and decoding are a bit-or and taking the low
+// byte, the encoding preserves order, and the packed three-input
+// half-precision maximum/minimum then takes the extremum of three pixel
+// pairs in one instruction, exactly.  No NaN, infinity or -0 can arise.
 // ---------------------------------------------------------------------------
-typedef unsigned short gc_u16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 gc_f16x2 __attribute__((ext_vector_type(2)));
+
+constexpr uint32_t PK_BIAS = 0x64006400u;  // 1024 in both halves
 
 template <int OP> struct PackedPick;
 template <> struct PackedPick<OP_DILATE> {
+    static __device__ __forceinline__ gc_f16x2 hx(uint32_t a) { return __builtin_bit_cast(gc_f16x2, a); }
     static __device__ __forceinline__ uint32_t pick(uint32_t a, uint32_t b) {
-        return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(gc_u16x2, a),
-                                                                      __builtin_bit_cast(gc_u16x2, b)));
+        return __builtin_bit_cast(uint32_t, __builtin_elementwise_maximum(hx(a), hx(b)));
+    }
+    static __device__ __forceinline__ uint32_t pick3(uint32_t a, uint32_t b, uint32_t c) {
+        return __builtin_bit_cast(uint32_t,
+                                  __builtin_elementwise_maximum(__builtin_elementwise_maximum(hx(a), hx(b)), hx(c)));
     }
     static __device__ __forceinline__ uint32_t clamp(uint32_t a, uint32_t b) {
-        return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(gc_u16x2, a),
-                                                                      __builtin_bit_cast(gc_u16x2, b)));
+        return __builtin_bit_cast(uint32_t, __builtin_elementwise_minimum(hx(a), hx(b)));
     }
 };
 template <> struct PackedPick<OP_ERODE> {
+    static __device__ __forceinline__ gc_f16x2 hx(uint32_t a) { return __builtin_bit_cast(gc_f16x2, a); }
     static __device__ __forceinline__ uint32_t pick(uint32_t a, uint32_t b) {
         return PackedPick<OP_DILATE>::clamp(a, b);
+    }
+    static __device__ __forceinline__ uint32_t pick3(uint32_t a, uint32_t b, uint32_t c) {
+        return __builtin_bit_cast(uint32_t,
+                                  __builtin_elementwise_minimum(__builtin_elementwise_minimum(hx(a), hx(b)), hx(c)));
     }
     static __device__ __forceinline__ uint32_t clamp(uint32_t a, uint32_t b) {
         return PackedPick<OP_DILATE>::pick(a, b);
     }
 };
 
-__device__ __forceinline__ uint32_t pack_rows(uint32_t lo, uint32_t hi) { return lo | (hi << 16); }
+// Two u8 values (0..255) -> one register of encoded halves.
+__device__ __forceinline__ uint32_t pack_rows(uint32_t lo, uint32_t hi) { return lo | (hi << 16) | PK_BIAS; }
 
+// Lanes per column group: 64 (one group) or 32 (two groups).
 template <int OP, int MODE, bool CLAMP, bool DETECT, int RPW, int NW>
 __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int rx0, int ry0,
                                                         uint32_t (*xch)[NW][2][128]) {
@@ -724,9 +741,8 @@ __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int 
         auto row_pass = [&](int j) {
             const uint32_t left = lane_shift<DPP_WAVE_SHR1>(v[j][1]);
             const uint32_t right = lane_shift<DPP_WAVE_SHL1>(v[j][0]);
-            const uint32_t t = P::pick(v[j][0], v[j][1]);
-            h[j][0] = P::pick(t, left);
-            h[j][1] = P::pick(t, right);
+            h[j][0] = P::pick3(left, v[j][0], v[j][1]);
+            h[j][1] = P::pick3(v[j][0], v[j][1], right);
         };
         auto publish = [&](int par) {
 #pragma unroll
@@ -763,12 +779,8 @@ __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int 
             uint64_t changed = 0;
 #pragma unroll
             for (int c = 0; c < CW; ++c) {
-                // middle registers: pairs share their extremum
 #pragma unroll
-                for (int j = 1; j < H - 1; ++j) {
-                    const uint32_t up = h[j - 1][c], dn = h[j + 1][c];
-                    finish(j, c, P::pick(P::pick(up, h[j][c]), dn), nv, changed);
-                }
+                for (int j = 1; j < H - 1; ++j) finish(j, c, P::pick3(h[j - 1][c], h[j][c], h[j + 1][c]), nv, changed);
             }
 #pragma unroll
             for (int c = 0; c < CW; ++c) {
@@ -778,10 +790,10 @@ __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int 
                 const uint32_t up0 = __builtin_amdgcn_alignbit(h[H - 1][c], above[c], 16);
                 const uint32_t dnl = __builtin_amdgcn_alignbit(below[c], h[0][c], 16);
                 if constexpr (H == 1) {
-                    finish(0, c, P::pick(P::pick(up0, h[0][c]), dnl), nv, changed);
+                    finish(0, c, P::pick3(up0, h[0][c], dnl), nv, changed);
                 } else {
-                    finish(0, c, P::pick(P::pick(up0, h[0][c]), h[1][c]), nv, changed);
-                    finish(H - 1, c, P::pick(P::pick(h[H - 2][c], h[H - 1][c]), dnl), nv, changed);
+                    finish(0, c, P::pick3(up0, h[0][c], h[1][c]), nv, changed);
+                    finish(H - 1, c, P::pick3(h[H - 2][c], h[H - 1][c], dnl), nv, changed);
                 }
             }
 #pragma unroll
