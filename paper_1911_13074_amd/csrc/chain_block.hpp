@@ -174,6 +174,25 @@ struct BlockArgs {
 // Runs a.k steps on the region whose top-left corner is (rx0, ry0) and
 // writes its core (offset a.halo, size core_x x core_y).  With DETECT, returns
 // this wave's change bits (bit s: some core pixel changed at step s).
+// A lane's CW adjacent exchange values in one LDS access where they span 8
+// or 16 bytes (the exchange rows are 16-byte aligned): one 64-bit read
+// instead of two interleaved 32-bit ones, which would meet two-way bank
+// conflicts.
+template <int CW, typename R>
+__device__ __forceinline__ void read_cols(const R *p, R (&out)[CW]) {
+    constexpr int B = CW * (int)sizeof(R);
+    if constexpr (B == 8) {
+        const uint2 v = *reinterpret_cast<const uint2 *>(p);
+        __builtin_memcpy(out, &v, B);
+    } else if constexpr (B == 16) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(p);
+        __builtin_memcpy(out, &v, B);
+    } else {
+#pragma unroll
+        for (int c = 0; c < CW; ++c) out[c] = p[c];
+    }
+}
+
 template <typename T, int OP, int MODE, bool CLAMP, bool DETECT, int CW, int RPW, int NW>
 __device__ __forceinline__ uint32_t chain_block_body(const BlockArgs &a, int rx0, int ry0,
                                                      typename RegOf<T>::type (*xch)[NW][2][64 * CW]) {
@@ -313,11 +332,8 @@ __device__ __forceinline__ uint32_t chain_block_body(const BlockArgs &a, int rx0
                 xch[par][w][1][lane * CW + c] = h[RPW - 1][c];
             }
             __syncthreads();
-#pragma unroll
-            for (int c = 0; c < CW; ++c) {
-                above[c] = xch[par][wa][1][lane * CW + c];
-                below[c] = xch[par][wb][0][lane * CW + c];
-            }
+            read_cols<CW>(&xch[par][wa][1][lane * CW], above);
+            read_cols<CW>(&xch[par][wb][0][lane * CW], below);
         };
         // ---- column pass + clamp of one row ----
         auto column_pass = [&](int r, R (&nv)[RPW][CW], uint64_t &changed) {
@@ -751,11 +767,8 @@ __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int 
                 xch[par][w][1][lane * CW + c] = h[H - 1][c];
             }
             __syncthreads();
-#pragma unroll
-            for (int c = 0; c < CW; ++c) {
-                above[c] = xch[par][wa][1][lane * CW + c];
-                below[c] = xch[par][wb][0][lane * CW + c];
-            }
+            read_cols<CW>(&xch[par][wa][1][lane * CW], above);
+            read_cols<CW>(&xch[par][wb][0][lane * CW], below);
         };
         // 16-bit row masks of the core for register j (low and high rows)
         auto core_mask = [&](int j) {
@@ -860,7 +873,7 @@ __device__ __forceinline__ uint32_t chain_block_dispatch(
             return chain_block_body_g2<T, OP, MODE, true, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
         }
     } else if constexpr (std::is_same<T, uint8_t>::value && CW == 2 && RPW % 2 == 0) {
-        // u8: two rows per register, packed 16-bit max/min
+        // u8: two rows per register, packed half-precision extrema on encoded pixels
         if constexpr (MODE == MODE_PLAIN) {
             const bool inside = rx0 >= 0 && ry0 >= 0 && rx0 + RX <= a.width && ry0 + RY <= a.height;
             if (inside) return chain_block_body_pk<OP, MODE, false, DETECT, RPW, NW>(a, rx0, ry0, xch);
@@ -889,7 +902,7 @@ __global__ __launch_bounds__(64 * NW) void chain_block_kernel(BlockArgs a) {
     const int rx0 = tx * a.core_x - a.halo;
     const int ry0 = ty * a.core_y - a.halo;
     using R = typename RegOf<T>::type;
-    __shared__ R xch[2][NW][2 * G][lanes_per_group<G>() * CW];
+    __shared__ __attribute__((aligned(16))) R xch[2][NW][2 * G][lanes_per_group<G>() * CW];
     const uint32_t bits = chain_block_dispatch<T, OP, MODE, DETECT, CW, RPW, NW, G>(a, rx0, ry0, xch);
     if constexpr (DETECT) {
         if (bits != 0 && (threadIdx.x & 63) == 0) atomicOr(a.change_word, bits);

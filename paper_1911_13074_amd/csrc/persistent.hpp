@@ -88,7 +88,7 @@ __device__ __forceinline__ bool wait_neighbours(const PersistentArgs &a, const P
 template <typename T, int OP, int MODE, int CW, int RPW, int NW, int G = 1>
 __global__ __launch_bounds__(64 * NW) void persistent_chain_kernel(PersistentArgs a) {
     using R = typename RegOf<T>::type;
-    __shared__ R xch[2][NW][2 * G][lanes_per_group<G>() * CW];
+    __shared__ __attribute__((aligned(16))) R xch[2][NW][2 * G][lanes_per_group<G>() * CW];
 
     const int tid = threadIdx.x;
     // Items are dealt round-robin: workgroup g takes g, g + G, g + 2G, ...
