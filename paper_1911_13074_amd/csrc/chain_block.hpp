@@ -795,6 +795,9 @@ __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int 
 #pragma unroll
                 for (int j = 1; j < H - 1; ++j) finish(j, c, P::pick3(h[j - 1][c], h[j][c], h[j + 1][c]), nv, changed);
             }
+            // keep the seams, which wait for the exchange reads, after the
+            // middle registers, which cover the reads' latency
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int c = 0; c < CW; ++c) {
                 // seams: rows above register 0 are (wave above's last row,
