@@ -33,6 +33,9 @@ import workloads  # noqa: E402
 # half-precision maximum/minimum (exact for 8-bit values), performs four
 # compare-selects per lane-op at full rate.
 PEAK_TCMP = 256 * 64 * 2.4e9 * 4 / 1e12   # 157.29 T compare-selects / s
+# HBM3E 8 TB/s; LDS 128 bytes per clock per CU.
+PEAK_HBM_GB_S = 8000
+PEAK_LDS_TB_S = 256 * 128 * 2.4e9 / 1e12   # 78.64 TB/s
 CMP_PER_PX_STEP_GEODESIC = 5
 CMP_PER_PX_STEP_PLAIN = 4
 
@@ -86,6 +89,7 @@ def kernel_profile(fn, steps):
 
 
 PROFILE = os.path.join(ROOT, "profiles", "chain_u8_1024_geodesic_dilation.md")
+PROFILE_SQ = os.path.join(ROOT, "profiles", "chain_u8_1024_sq_counters.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1911_13074_amd", "csrc", "chain_block.hpp")]
 
 
@@ -111,6 +115,28 @@ def profiled_traffic():
     if vals.get("kernel_source_sha256_16") != h.hexdigest()[:16]:
         return None, None
     return int(vals["traffic_bytes_per_dispatch"]), float(vals["avg_dispatch_ns"]) * 1e-6
+
+
+def profiled_values(path, keys):
+    """Machine-readable values of a committed rocprofv3 summary, or {} if
+    the kernel source has changed since it was taken."""
+    import hashlib
+    try:
+        text = open(path).read()
+    except OSError:
+        return {}
+    vals = {}
+    for line in text.splitlines():
+        line = line.strip()
+        if ":" in line and line.split(":")[0] in keys + ("kernel_source_sha256_16",):
+            k, v = line.split(":", 1)
+            vals[k] = v.strip()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    if vals.pop("kernel_source_sha256_16", None) != h.hexdigest()[:16]:
+        return {}
+    return {k: float(v) for k, v in vals.items()}
 
 
 def cpu_baseline(f, m, n_steps, repeats=3):
@@ -215,6 +241,19 @@ def main():
         "rocprof_avg_dispatch_ms": round(prof_ms, 5) if prof_ms else None,
         "algorithmic_bytes_per_launch": 3 * px,
     }
+    # Context beside the ALU bound: the kernel's HBM rate (profiled bytes
+    # per dispatch over the average launch) and its LDS exchange rate (bytes
+    # per dispatch from the profiled LDS instruction count).
+    if traffic:
+        hbm = traffic / (k_ms * 1e-3) / 1e9
+        roofline["hbm"] = {"achieved_gb_s": round(hbm, 1), "peak_gb_s": PEAK_HBM_GB_S,
+                           "frac": round(hbm / PEAK_HBM_GB_S, 4)}
+    sq = profiled_values(PROFILE_SQ, ("lds_bytes_per_dispatch", "valu_busy_pct"))
+    if sq:
+        lds = sq["lds_bytes_per_dispatch"] / (k_ms * 1e-3) / 1e12
+        roofline["lds"] = {"achieved_tb_s": round(lds, 2), "peak_tb_s": round(PEAK_LDS_TB_S, 2),
+                           "frac": round(lds / PEAK_LDS_TB_S, 4), "bytes_per_launch": int(sq["lds_bytes_per_dispatch"])}
+        roofline["valu_busy_pct"] = sq["valu_busy_pct"]
 
     extra = {}
     if not args.no_extra:
