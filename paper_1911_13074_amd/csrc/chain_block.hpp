@@ -730,14 +730,23 @@ __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int 
         }
     }
 
-    uint64_t col_in_core[CW];
+    // Change detection: per register, the bits of its core pixels (16-bit
+    // halves of core rows, in columns of the core).  A step changed the core
+    // iff some (new ^ old) & mask is nonzero; the encodings are unique, so
+    // equal bits mean equal pixels.
+    uint32_t cmask[DETECT ? H : 1][CW];
     if constexpr (DETECT) {
 #pragma unroll
-        for (int c = 0; c < CW; ++c) {
-            const int cx = lane * CW + c;
-            const int x = rx0 + cx;
-            const bool ok = cx >= halo && cx < halo + a.core_x && x < a.width;
-            col_in_core[c] = __builtin_amdgcn_ballot_w64(ok);
+        for (int j = 0; j < H; ++j) {
+            const int ry = w * RPW + j;
+            const bool lo = ry >= halo && ry < halo + a.core_y && ry0 + ry < a.height;
+            const bool hi = ry + H >= halo && ry + H < halo + a.core_y && ry0 + ry + H < a.height;
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                const int cx = lane * CW + c;
+                const bool col = cx >= halo && cx < halo + a.core_x && rx0 + cx < a.width;
+                cmask[j][c] = col ? ((lo ? 0x0000FFFFu : 0u) | (hi ? 0xFFFF0000u : 0u)) : 0u;
+            }
         }
     }
     uint32_t step_bits = 0;
@@ -770,17 +779,9 @@ __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int 
             read_cols<CW>(&xch[par][wa][1][lane * CW], above);
             read_cols<CW>(&xch[par][wb][0][lane * CW], below);
         };
-        // 16-bit row masks of the core for register j (low and high rows)
-        auto core_mask = [&](int j) {
-            const int ry = w * RPW + j;
-            const bool lo = ry >= halo && ry < halo + a.core_y && ry0 + ry < a.height;
-            const bool hi = ry + H >= halo && ry + H < halo + a.core_y && ry0 + ry + H < a.height;
-            return (lo ? 0x0000FFFFu : 0u) | (hi ? 0xFFFF0000u : 0u);
-        };
-        auto finish = [&](int j, int c, uint32_t x, uint32_t (&nv)[H][CW], uint64_t &changed) {
+        auto finish = [&](int j, int c, uint32_t x, uint32_t (&nv)[H][CW], uint32_t &changed) {
             if constexpr (CLAMP) x = P::clamp(x, m[j][c]);
-            if constexpr (D) changed |= __builtin_amdgcn_ballot_w64(((x ^ v[j][c]) & core_mask(j)) != 0) &
-                                        col_in_core[c];
+            if constexpr (D) changed |= (x ^ v[j][c]) & cmask[j][c];
             nv[j][c] = x;
         };
 
@@ -789,7 +790,7 @@ __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int 
         publish(0);
         for (int s = 0; s < busy; ++s) {
             uint32_t nv[H][CW];
-            uint64_t changed = 0;
+            uint32_t changed = 0;
 #pragma unroll
             for (int c = 0; c < CW; ++c) {
 #pragma unroll
@@ -817,7 +818,7 @@ __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int 
 #pragma unroll
                 for (int c = 0; c < CW; ++c) v[j][c] = nv[j][c];
             if constexpr (D) {
-                if (changed) step_bits |= 1u << s;
+                if (__builtin_amdgcn_ballot_w64(changed != 0)) step_bits |= 1u << s;
             }
             if (s + 1 < busy) {
                 row_pass(0);
