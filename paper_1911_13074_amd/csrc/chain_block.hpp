@@ -362,6 +362,9 @@ __device__ __forceinline__ uint32_t chain_block_body(const BlockArgs &a, int rx0
             uint64_t changed = 0;
 #pragma unroll
             for (int r = 1; r < RPW - 1; ++r) column_pass(r, nv, changed);
+            // the edge rows, which wait for the exchange reads, after the
+            // middle rows, which cover the reads' latency
+            __builtin_amdgcn_sched_barrier(0);
             column_pass(0, nv, changed);
             if constexpr (RPW > 1) column_pass(RPW - 1, nv, changed);
 #pragma unroll
