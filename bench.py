@@ -409,6 +409,10 @@ def main():
     # 4-thread CPU; it reports no time for this exact workload.
     extra["paper_context"] = {"claim_gpx_steps_per_s": 47.2,
                               "claim": ">= 30 FPS for 1500-filter chains on 1024x1024 images",
+                              "claim_hardware": "the paper's test systems (its Table 1): Intel Core i5-6600K "
+                                                "3.4 GHz (4 cores); AMD Threadripper 1920X 3.5 GHz (12 cores, "
+                                                "SMT); 2x Intel Xeon E5-2683 v4 2.1 GHz (2x16 cores, SMT); the "
+                                                "claim rests on the best operator times across them",
                               "value_over_claim": round(value / 47.2, 1)}
     if "batched_64_uneven_u8" in extra:
         # the metric's two ratios: each workload's rate over the plain chain's
