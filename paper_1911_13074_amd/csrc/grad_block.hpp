@@ -84,11 +84,15 @@ constexpr int GB_CX = GB_RW - 2 * GB_K;        // core width (48)
 constexpr int GB_WR = 8;                       // rows per wave
 
 template <typename T> struct GradTile {
-    // f64 tiles are shorter so that two state planes and the codes fit LDS.
+    // f64 tiles are shorter so that the backward's code planes and 64-bit
+    // edge exchange still let two workgroups share a CU's LDS.
     static constexpr int NW = sizeof(T) == 8 ? 12 : 16;   // waves
     static constexpr int RH = NW * GB_WR;                 // region height
     static constexpr int CY = RH - 2 * GB_K;              // core height
     static constexpr int THREADS = 64 * NW;
+    // Waves per SIMD the codes kernel is compiled for: two f32 workgroups
+    // per CU (at most 64 VGPRs); f64 keeps its register budget.
+    static constexpr int CODES_WAVES_PER_SIMD = sizeof(T) == 8 ? 1 : 8;
 };
 
 struct GradBlockArgs {
@@ -142,7 +146,8 @@ __device__ __forceinline__ bool gb_wave_busy(int w, int k, int s) {
 // step.  The codes of a step are staged in LDS (double-buffered) and stored
 // as 16-byte rows after the next step's barrier.
 template <typename T, int OP>
-__global__ __launch_bounds__(GradTile<T>::THREADS) void block_codes_kernel(GradBlockArgs a) {
+__global__ __launch_bounds__(GradTile<T>::THREADS, GradTile<T>::CODES_WAVES_PER_SIMD) void block_codes_kernel(
+    GradBlockArgs a) {
     using B = Bounds<T, OP>;
     using G = GradTile<T>;
     constexpr int CY = G::CY, NW = G::NW;
