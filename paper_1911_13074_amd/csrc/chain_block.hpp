@@ -193,7 +193,29 @@ __device__ __forceinline__ void read_cols(const R *p, R (&out)[CW]) {
     }
 }
 
-template <typename T, int OP, int MODE, bool CLAMP, bool DETECT, int CW, int RPW, int NW>
+// Core stores coherent at agent scope on their own (relaxed agent-scope
+// atomic stores), for kernels that publish tiles to other workgroups: the
+// release that follows then has (almost) nothing left to write back.
+template <typename U>
+__device__ __forceinline__ void agent_store(U *p, U v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void agent_store_pair(uint8_t *p, uint32_t a, uint32_t b) {
+    agent_store(reinterpret_cast<uint16_t *>(p), (uint16_t)(a | (b << 8)));
+}
+__device__ __forceinline__ void agent_store_pair(float *p, float a, float b) {
+    agent_store(reinterpret_cast<uint64_t *>(p),
+                (uint64_t)__builtin_bit_cast(uint32_t, a) | ((uint64_t)__builtin_bit_cast(uint32_t, b) << 32));
+}
+__device__ __forceinline__ void agent_store_pair(double *p, double a, double b) {
+    agent_store(p, a);
+    agent_store(p + 1, b);
+}
+__device__ __forceinline__ void agent_store_reg(uint8_t *p, uint32_t v) { agent_store(p, (uint8_t)v); }
+__device__ __forceinline__ void agent_store_reg(float *p, float v) { agent_store(p, v); }
+__device__ __forceinline__ void agent_store_reg(double *p, double v) { agent_store(p, v); }
+
+template <typename T, int OP, int MODE, bool CLAMP, bool DETECT, int CW, int RPW, int NW, bool AGENT_STORES = false>
 __device__ __forceinline__ uint32_t chain_block_body(const BlockArgs &a, int rx0, int ry0,
                                                      typename RegOf<T>::type (*xch)[NW][2][64 * CW]) {
     using R = typename RegOf<T>::type;
@@ -406,8 +428,15 @@ __device__ __forceinline__ uint32_t chain_block_body(const BlockArgs &a, int rx0
             const bool in0 = cx >= halo && cx < halo + a.core_x && x < a.width;
             const bool in1 = cx + 1 >= halo && cx + 1 < halo + a.core_x && x + 1 < a.width;
             if (in0 && in1 && (fast || pair_aligned(p))) {
-                using PT = typename Pair<T>::type;
-                *reinterpret_cast<PT *>(p) = make_pair(v[r][0], v[r][1], p);
+                if constexpr (AGENT_STORES) {
+                    agent_store_pair(p, v[r][0], v[r][1]);
+                } else {
+                    using PT = typename Pair<T>::type;
+                    *reinterpret_cast<PT *>(p) = make_pair(v[r][0], v[r][1], p);
+                }
+            } else if constexpr (AGENT_STORES) {
+                if (in0) agent_store_reg(p, v[r][0]);
+                if (in1) agent_store_reg(p + 1, v[r][1]);
             } else {
                 if (in0) from_reg(p, v[r][0]);
                 if (in1) from_reg(p + 1, v[r][1]);
@@ -417,8 +446,12 @@ __device__ __forceinline__ uint32_t chain_block_body(const BlockArgs &a, int rx0
             for (int c = 0; c < CW; ++c) {
                 const int cx = lane * CW + c;
                 const int x = rx0 + cx;
-                if (cx >= halo && cx < halo + a.core_x && x < a.width)
-                    from_reg(dst + (int64_t)y * a.pitch + x, v[r][c]);
+                if (cx >= halo && cx < halo + a.core_x && x < a.width) {
+                    if constexpr (AGENT_STORES)
+                        agent_store_reg(dst + (int64_t)y * a.pitch + x, v[r][c]);
+                    else
+                        from_reg(dst + (int64_t)y * a.pitch + x, v[r][c]);
+                }
             }
         }
     }
@@ -664,7 +697,7 @@ template <> struct PackedPick<OP_ERODE> {
 __device__ __forceinline__ uint32_t pack_rows(uint32_t lo, uint32_t hi) { return lo | (hi << 16) | PK_BIAS; }
 
 // Lanes per column group: 64 (one group) or 32 (two groups).
-template <int OP, int MODE, bool CLAMP, bool DETECT, int RPW, int NW>
+template <int OP, int MODE, bool CLAMP, bool DETECT, int RPW, int NW, bool AGENT_STORES = false>
 __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int rx0, int ry0,
                                                         uint32_t (*xch)[NW][2][128]) {
     static_assert(RPW % 2 == 0, "two rows per register");
@@ -853,7 +886,17 @@ __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int 
         uint8_t *p = dst + (int64_t)y * a.pitch + x;
         const bool in0 = cx >= halo && cx < halo + a.core_x && x < a.width;
         const bool in1 = cx + 1 >= halo && cx + 1 < halo + a.core_x && x + 1 < a.width;
-        if (in0 && in1 && (fast || pair_aligned(p))) {
+        if constexpr (AGENT_STORES) {
+            // coherent at agent scope on their own, so the release that
+            // publishes the tile finds (almost) nothing to write back
+            if (in0 && in1 && (fast || pair_aligned(p))) {
+                __hip_atomic_store(reinterpret_cast<uint16_t *>(p), (uint16_t)(c0 | (c1 << 8)), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                if (in0) __hip_atomic_store(p, (uint8_t)c0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (in1) __hip_atomic_store(p + 1, (uint8_t)c1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        } else if (in0 && in1 && (fast || pair_aligned(p))) {
             *reinterpret_cast<uint16_t *>(p) = (uint16_t)(c0 | (c1 << 8));
         } else {
             if (in0) *p = (uint8_t)c0;
@@ -866,7 +909,10 @@ __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int 
 template <int G> constexpr int lanes_per_group() { return 64 / G; }
 
 // Plain chains skip the border fence for regions entirely inside the image.
-template <typename T, int OP, int MODE, bool DETECT, int CW, int RPW, int NW, int G = 1>
+// AGENT_STORES: the core is written with agent-scope stores (packed and
+// generic bodies; the persistent kernel, which publishes tiles to other
+// workgroups).
+template <typename T, int OP, int MODE, bool DETECT, int CW, int RPW, int NW, int G = 1, bool AGENT_STORES = false>
 __device__ __forceinline__ uint32_t chain_block_dispatch(
     const BlockArgs &a, int rx0, int ry0, typename RegOf<T>::type (*xch)[NW][2 * G][lanes_per_group<G>() * CW]) {
     constexpr int RX = lanes_per_group<G>() * CW;
@@ -883,17 +929,17 @@ __device__ __forceinline__ uint32_t chain_block_dispatch(
         // u8: two rows per register, packed half-precision extrema on encoded pixels
         if constexpr (MODE == MODE_PLAIN) {
             const bool inside = rx0 >= 0 && ry0 >= 0 && rx0 + RX <= a.width && ry0 + RY <= a.height;
-            if (inside) return chain_block_body_pk<OP, MODE, false, DETECT, RPW, NW>(a, rx0, ry0, xch);
-            return chain_block_body_pk<OP, MODE, true, DETECT, RPW, NW>(a, rx0, ry0, xch);
+            if (inside) return chain_block_body_pk<OP, MODE, false, DETECT, RPW, NW, AGENT_STORES>(a, rx0, ry0, xch);
+            return chain_block_body_pk<OP, MODE, true, DETECT, RPW, NW, AGENT_STORES>(a, rx0, ry0, xch);
         } else {
-            return chain_block_body_pk<OP, MODE, true, DETECT, RPW, NW>(a, rx0, ry0, xch);
+            return chain_block_body_pk<OP, MODE, true, DETECT, RPW, NW, AGENT_STORES>(a, rx0, ry0, xch);
         }
     } else if constexpr (MODE == MODE_PLAIN) {
         const bool inside = rx0 >= 0 && ry0 >= 0 && rx0 + RX <= a.width && ry0 + RY <= a.height;
-        if (inside) return chain_block_body<T, OP, MODE, false, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
-        return chain_block_body<T, OP, MODE, true, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
+        if (inside) return chain_block_body<T, OP, MODE, false, DETECT, CW, RPW, NW, AGENT_STORES>(a, rx0, ry0, xch);
+        return chain_block_body<T, OP, MODE, true, DETECT, CW, RPW, NW, AGENT_STORES>(a, rx0, ry0, xch);
     } else {
-        return chain_block_body<T, OP, MODE, true, DETECT, CW, RPW, NW>(a, rx0, ry0, xch);
+        return chain_block_body<T, OP, MODE, true, DETECT, CW, RPW, NW, AGENT_STORES>(a, rx0, ry0, xch);
     }
 }
 

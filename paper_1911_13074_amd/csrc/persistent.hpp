@@ -136,7 +136,11 @@ __global__ __launch_bounds__(64 * NW) void persistent_chain_kernel(PersistentArg
         ba.tiles_x = im.tiles_x;
         const int rx0 = tx * im.core_x - im.k;
         const int ry0 = ty * im.core_y - im.k;
-        chain_block_dispatch<T, OP, MODE, false, CW, RPW, NW, G>(ba, rx0, ry0, xch);
+        // The core goes out with agent-scope stores: they reach the level
+        // that every XCD sees by themselves, so the agent-scope release below
+        // has (almost) no dirty L2 lines to write back.  The release is still
+        // what orders them before the counter.
+        chain_block_dispatch<T, OP, MODE, false, CW, RPW, NW, G, true>(ba, rx0, ry0, xch);
 
         // ---- publish: stores first, then the tile's counter ----
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
