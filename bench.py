@@ -147,9 +147,9 @@ def cpu_baseline(f, m, n_steps, repeats=3):
     threads = oracle.max_threads()
     t0 = time.perf_counter()
     for _ in range(repeats):
-        oracle.chain(oracle.DILATE, f, n_steps, m)
+        ref = oracle.chain(oracle.DILATE, f, n_steps, m)
     dt = (time.perf_counter() - t0) / repeats
-    return {
+    return ref, {
         "value": round(f.size * n_steps / dt / 1e9, 4),
         "unit": "Gpixel-steps/s",
         "cores": threads,
@@ -158,6 +158,67 @@ def cpu_baseline(f, m, n_steps, repeats=3):
                   f"(the benchmark workload in full), {repeats} runs of the plain C oracle, "
                   f"OpenMP over rows on {threads} threads, {dt:.2f} s per run",
     }
+
+
+def verify(S, N, F, M, f, m, headline_ref, dev, with_extra=True, batch_outs=None):
+    """Bitwise parity with the oracle of what the run measured: each GPU
+    result is computed once more, untimed, and compared element by element
+    (and by step count where there is one).  The headline's oracle result is
+    the CPU baseline's own.  Of the batch every 16th image is checked; the
+    gradient's parity is left to the test suite (its oracle takes minutes
+    at this size).  The batch's images are those of the timed plan's last
+    replay."""
+    import oracle
+    import paper_1911_13074_amd as gc
+
+    def host(t):
+        torch.cuda.synchronize()
+        return t.cpu().numpy()
+
+    def on_dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    ok = {"geodesic_dilation_1500": bool(np.array_equal(host(gc.geodesic_dilate_chain(F, M, N)), headline_ref))}
+    if not with_extra:
+        return ok
+    fe, me = workloads.headline_u8_erosion(size=S)
+    ok["geodesic_erosion_1500"] = bool(np.array_equal(
+        host(gc.geodesic_erode_chain(on_dev(fe), on_dev(me), N)), oracle.chain(oracle.ERODE, fe, N, me)))
+    g, gs, _ = gc.reconstruct_by_dilation(F, M)
+    r, rs, _ = oracle.reconstruct(oracle.DILATE, f, m)
+    ok["reconstruction_by_dilation"] = bool(np.array_equal(host(g), r)) and gs == rs
+    fo = workloads.operator_u8(size=S)
+    FO = on_dev(fo)
+    for name, gpu, ref in (("hmax_40", lambda: gc.hmax(FO, 40), lambda: oracle.hmax(fo, 40)),
+                           ("dome_40", lambda: gc.dome(FO, 40), lambda: oracle.dome(fo, 40)),
+                           ("hfill", lambda: gc.hfill(FO), lambda: oracle.hfill(fo)),
+                           ("raobj", lambda: gc.raobj(FO), lambda: oracle.raobj(fo)),
+                           ("open_rec_5", lambda: gc.open_by_reconstruction(FO, 5),
+                            lambda: oracle.open_by_reconstruction(fo, 5)),
+                           ("open_rec_75", lambda: gc.open_by_reconstruction(FO, 75),
+                            lambda: oracle.open_by_reconstruction(fo, 75))):
+        g, gs, _ = gpu()
+        r, rs, _ = ref()
+        ok[name] = bool(np.array_equal(host(g), r)) and gs == rs
+    gd, _, ge, gt = gc.quasi_distance(FO, lipschitz=True)
+    dl1, _, _, re_, rt = oracle.quasi_distance(fo)
+    ok["qdt"] = bool(np.array_equal(host(gd), dl1)) and (ge, gt) == (re_, rt)
+    G, _ = gc.granulometry(FO, 11)
+    Go, _ = oracle.granulometry(fo, 11)
+    ok["pattern_spectrum_0_11"] = [float(x) for x in G] == [float(x) for x in Go]   # u8 sums are exact
+    ok["asf_11"] = bool(np.array_equal(host(gc.asf(FO, 11)), oracle.asf(fo, 11)))
+    for dt, name in ((np.uint8, "u8"), (np.float32, "f32"), (np.float64, "f64")):
+        x = workloads.plain_input(dt, size=S)
+        X = on_dev(x)
+        for n in (13, 91, 183):
+            ok[f"plain_dilation_{name}_{n}"] = bool(np.array_equal(host(gc.dilate_chain(X, n)),
+                                                                   oracle.chain(oracle.DILATE, x, n)))
+    if batch_outs:
+        items = workloads.batch_u8().items
+        ok["batched_64_uneven_u8_every_16th"] = all(
+            bool(np.array_equal(o, oracle.chain(oracle.DILATE, items[i].marker, items[i].n_steps, items[i].mask)))
+            for i, o in batch_outs.items())
+    return ok
 
 
 def cpu_single_thread(f, m, n_steps):
@@ -256,6 +317,7 @@ def main():
         roofline["valu_busy_pct"] = sq["valu_busy_pct"]
 
     extra = {}
+    batch_outs = None
     if not args.no_extra:
         fe, me = workloads.headline_u8_erosion(size=S)
         Fe, Me = torch.from_numpy(fe).to(dev), torch.from_numpy(me).to(dev)
@@ -334,6 +396,8 @@ def main():
             "vs_plain": round(rate_b / value, 3), "autotuned": True, "tuning_s": round(tune_s, 1),
             "tile_family": info["tile"], "block_steps": info["block_steps"], "workgroups": info["workgroups"],
             "builtin_plan_gpx_steps_per_s": round(batch.px_steps / ms_d / 1e6, 2)}
+        torch.cuda.synchronize()
+        batch_outs = {i: plan.outs[i].cpu().numpy() for i in range(0, len(items), 16)}
         plan.close()
         del items
         # Differentiable: 16 x 1024^2 f32, 200 steps, forward + backward.
@@ -402,11 +466,13 @@ def main():
         "roofline": roofline,
     }
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(f, m, N)
+        headline_ref, line["cpu_baseline"] = cpu_baseline(f, m, N)
         extra["cpu_oracle_1_thread"] = cpu_single_thread(f, m, 150)
+        line["parity"] = verify(S, N, F, M, f, m, headline_ref, dev, with_extra=not args.no_extra,
+                                batch_outs=batch_outs)
     # Context, not a baseline: the paper claims real time (30 FPS) for chains
     # of 1500 filters on 1024^2 images, i.e. at least 47.2 Gpx-steps/s on its
-    # 4-thread CPU; it reports no time for this exact workload.
+    # test CPUs; it reports no time for this exact workload.
     extra["paper_context"] = {"claim_gpx_steps_per_s": 47.2,
                               "claim": ">= 30 FPS for 1500-filter chains on 1024x1024 images",
                               "claim_hardware": "the paper's test systems (its Table 1): Intel Core i5-6600K "
@@ -420,6 +486,10 @@ def main():
                             "fwd_bwd_16x1024_f32_200": extra["fwd_bwd_16x1024_f32_200"]["vs_plain"]}
     line["extra"] = extra
     print(json.dumps(line), flush=True)
+    if "parity" in line and not all(line["parity"].values()):
+        bad = [k for k, v in line["parity"].items() if not v]
+        print(f"bench.py: results differ from the oracle: {bad}", file=sys.stderr)
+        sys.exit(1)
 
 
 if __name__ == "__main__":
