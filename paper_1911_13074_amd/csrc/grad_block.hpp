@@ -54,6 +54,14 @@ __device__ __forceinline__ bool better(T a, T b) {
     return OP == OP_DILATE ? (a > b) : (a < b);
 }
 
+// Extremum of two values (max for dilation, min for erosion); values are
+// finite, so max3/min3 forms apply.
+template <int OP, typename T>
+__device__ __forceinline__ T extremum(T a, T b) {
+    if constexpr (OP == OP_DILATE) return a > b ? a : b;
+    else return a < b ? a : b;
+}
+
 // Value of the adjacent lane (lane = region column): WAVE_SHR1 gives column
 // x - 1, WAVE_SHL1 column x + 1.  Lanes 0 / 63 receive 0: they are the
 // region's outer columns, whose results are wrong anyway and never reach the
@@ -188,14 +196,14 @@ __global__ __launch_bounds__(GradTile<T>::THREADS, GradTile<T>::CODES_WAVES_PER_
             // row pass: first extremum of (x-1, x, x+1) and its dx index
 #pragma unroll
             for (int r = 0; r < GB_WR; ++r) {
+                // the first of (x-1, x, x+1) equal to their extremum is the
+                // first extremum in raster order
                 const T c = v[r];
-                T best = gb_shift<DPP_WAVE_SHR1>(c);
+                const T left = gb_shift<DPP_WAVE_SHR1>(c);
                 const T right = gb_shift<DPP_WAVE_SHL1>(c);
-                int i = 0;
-                if (better<OP>(c, best)) { best = c; i = 1; }
-                if (better<OP>(right, best)) { best = right; i = 2; }
+                const T best = extremum<OP>(extremum<OP>(left, c), right);
                 h[r] = best;
-                ix[r] = i;
+                ix[r] = left == best ? 0 : (c == best ? 1 : 2);
             }
             xv[par][w][0][x] = h[0];
             xi[par][w][0][x] = (uint8_t)ix[0];
@@ -212,12 +220,12 @@ __global__ __launch_bounds__(GradTile<T>::THREADS, GradTile<T>::CODES_WAVES_PER_
             // then the clamp (the mask wins ties)
 #pragma unroll
             for (int r = 0; r < GB_WR; ++r) {
-                T best = r == 0 ? ha : h[r - 1];
-                int code = r == 0 ? ia : ix[r - 1];
-                if (better<OP>(h[r], best)) { best = h[r]; code = 3 + ix[r]; }
+                const T hu = r == 0 ? ha : h[r - 1];
+                const int iu = r == 0 ? ia : ix[r - 1];
                 const T hd = r == GB_WR - 1 ? hb : h[r + 1];
                 const int id = r == GB_WR - 1 ? ib : ix[r + 1];
-                if (better<OP>(hd, best)) { best = hd; code = 6 + id; }
+                const T best = extremum<OP>(extremum<OP>(hu, h[r]), hd);
+                const int code = hu == best ? iu : (h[r] == best ? 3 + ix[r] : 6 + id);
                 const bool mask_wins = OP == OP_DILATE ? !(best < m[r]) : !(best > m[r]);
                 v[r] = mask_wins ? m[r] : best;
                 const int cy = w * GB_WR + r - GB_K;
