@@ -348,6 +348,19 @@ int gc_set_tuning(int32_t block_steps, int32_t tile);
 int gc_set_window_path(int32_t min_steps);
 
 /* ---------------------------------------------------------------------
+ * Optional value check before a call.  The definitions (Section 2) are over
+ * ordered values; NaN is not one, and the gradient entry points also need
+ * finite values (the region's outside is held at -inf / +inf, which must
+ * never tie with a pixel).  gc_validate_values scans a device image and
+ * returns GC_ERR_INVALID_ARG if a pixel is a NaN, or an infinity when
+ * allow_inf == 0 (gc_last_error says which); GC_OK otherwise, and always
+ * for u8 and empty images.  Synchronises hip_stream (it reads one word
+ * back).  The chain entry points do not call it themselves.
+ * ------------------------------------------------------------------- */
+int gc_validate_values(gc_dtype dtype, const void *image, gc_shape shape, int32_t allow_inf,
+                       void *hip_stream);
+
+/* ---------------------------------------------------------------------
  * Measurement hook.  While enabled (on != 0), every kernel launch made by
  * the entry points above is bracketed by two HIP events recorded on the
  * launch stream.  gc_profile_read waits for the last event, returns the sum

@@ -29,4 +29,5 @@ from .ops import (  # noqa: F401
     reconstruct_by_erosion,
     set_tuning,
     set_window_path,
+    validate_values,
 )

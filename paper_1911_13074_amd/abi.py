@@ -65,6 +65,7 @@ SIGNATURES = {
     "gc_asf": (ctypes.c_int, [_DT, _VP, _VP, gc_shape, _I32, _VP]),
     "gc_set_tuning": (ctypes.c_int, [_I32, _I32]),
     "gc_set_window_path": (ctypes.c_int, [_I32]),
+    "gc_validate_values": (ctypes.c_int, [_DT, _VP, gc_shape, _I32, _VP]),
     "gc_plan_create": (ctypes.c_int, [_DT, _DT, ctypes.POINTER(gc_item), _I32,
                                       ctypes.POINTER(ctypes.c_void_p)]),
     "gc_plan_launch": (ctypes.c_int, [_VP, _VP]),

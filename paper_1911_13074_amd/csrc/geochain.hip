@@ -1609,6 +1609,27 @@ static int run_bwd(gc_dtype dtype, const uint8_t *codes, const void *g_out, void
 
 using namespace geochain;
 
+template <typename T>
+static int run_value_scan_t(const T *img, const gc_shape &s, uint32_t *found, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    Workspace *ws = nullptr;
+    int rc = get_workspace(stream, 0, 1, &ws);
+    if (rc != GC_OK) return rc;
+    const bool vec = rows_aligned16(s, sizeof(T), img, img);
+    const PixelArgs<T> p = pixel_args<T>(s, img, nullptr, nullptr, vec);
+    hipLaunchKernelGGL(fill_words_kernel, dim3(1), dim3(128), 0, st, ws->words, 1, 0u);
+    const int grid = px_grid(p.n_chunks, 4096);
+    if (vec)
+        hipLaunchKernelGGL((value_scan_kernel<T, true>), dim3(grid), dim3(PX_THREADS), 0, st, p, ws->words);
+    else
+        hipLaunchKernelGGL((value_scan_kernel<T, false>), dim3(grid), dim3(PX_THREADS), 0, st, p, ws->words);
+    GC_HIP(hipGetLastError());
+    GC_HIP(hipMemcpyAsync(ws->host_words, ws->words, 4, hipMemcpyDeviceToHost, st));
+    GC_HIP(hipStreamSynchronize(st));
+    *found = ws->host_words[0];
+    return GC_OK;
+}
+
 extern "C" {
 
 int gc_version(void) { return 100; }
@@ -2023,6 +2044,21 @@ int gc_profile_read(double *kernel_ms, int64_t *launches, int64_t *steps) {
     if (kernel_ms) *kernel_ms = total;
     if (launches) *launches = n;
     if (steps) *steps = nsteps;
+    return GC_OK;
+}
+
+int gc_validate_values(gc_dtype dtype, const void *image, gc_shape shape, int32_t allow_inf, void *hip_stream) {
+    g_last_error.clear();
+    int rc = validate_shape(dtype, shape);
+    if (rc != GC_OK) return rc;
+    if (dtype == GC_U8 || shape.width == 0 || shape.height == 0) return GC_OK;
+    if (!image) return fail(GC_ERR_INVALID_ARG, "null image pointer");
+    uint32_t found = 0;
+    rc = dtype == GC_F32 ? run_value_scan_t<float>((const float *)image, shape, &found, hip_stream)
+                         : run_value_scan_t<double>((const double *)image, shape, &found, hip_stream);
+    if (rc != GC_OK) return rc;
+    if (found & 1u) return fail(GC_ERR_INVALID_ARG, "the image holds a NaN");
+    if ((found & 2u) && !allow_inf) return fail(GC_ERR_INVALID_ARG, "the image holds an infinity");
     return GC_OK;
 }
 

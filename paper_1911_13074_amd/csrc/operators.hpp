@@ -205,4 +205,37 @@ __global__ __launch_bounds__(PX_THREADS) void sum_partials_kernel(const double *
     if (threadIdx.x == 0) out[0] = acc;
 }
 
+// ---------------------------------------------------------------------------
+// Value scan: bit 0 of flags[0] is set if some pixel is a NaN, bit 1 if some
+// pixel is an infinity.  The tests look at the bit patterns (exponent all
+// ones; mantissa nonzero for NaN, zero for an infinity), so they hold
+// whatever the compiler assumes about NaNs.  Findings are rare, so a thread
+// with one ORs it in directly.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t value_class(float x) {
+    const uint32_t a = __builtin_bit_cast(uint32_t, x) & 0x7FFFFFFFu;
+    return a > 0x7F800000u ? 1u : (a == 0x7F800000u ? 2u : 0u);
+}
+__device__ __forceinline__ uint32_t value_class(double x) {
+    const uint64_t a = __builtin_bit_cast(uint64_t, x) & 0x7FFFFFFFFFFFFFFFull;
+    return a > 0x7FF0000000000000ull ? 1u : (a == 0x7FF0000000000000ull ? 2u : 0u);
+}
+
+template <typename T, bool VEC>
+__global__ __launch_bounds__(PX_THREADS) void value_scan_kernel(PixelArgs<T> p, uint32_t *flags) {
+    constexpr int V = VEC ? 16 / (int)sizeof(T) : 1;
+    uint32_t bits = 0;
+    for_chunks<VEC>(p, [&](int64_t, int64_t, int64_t off, int nvalid) {
+        if (VEC && nvalid == V) {
+            Chunk<T, V> c;
+            c.v = *reinterpret_cast<const uint4 *>(p.a + off);
+#pragma unroll
+            for (int j = 0; j < V; ++j) bits |= value_class(c.e[j]);
+        } else {
+            for (int j = 0; j < nvalid; ++j) bits |= value_class(p.a[off + j]);
+        }
+    });
+    if (bits != 0) atomicOr(flags, bits);
+}
+
 }  // namespace geochain

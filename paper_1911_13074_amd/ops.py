@@ -221,6 +221,18 @@ def asf(f, s_max, out=None):
     return out
 
 
+def validate_values(x, allow_inf=True):
+    """Raise ValueError if the device image holds a NaN (or, with
+    allow_inf=False, an infinity); u8 images always pass.  Synchronises
+    the current stream."""
+    _check_image(x, "image")
+    with torch.cuda.device(x.device):
+        st = abi.gc_validate_values(_dtype_code(x), _ptr(x), _shape(x), int(bool(allow_inf)), _stream(x))
+    if st == abi.GC_ERR_INVALID_ARG:
+        raise ValueError(abi.last_error())
+    abi.check(st, "gc_validate_values")
+
+
 def set_window_path(min_steps: int = 0) -> None:
     """Plain chains of at least min_steps steps run as one separable
     (2n+1)^2 window (0: built-in threshold, -1: never)."""

@@ -167,3 +167,15 @@ def test_granulometry_and_asf_validation():
     assert abi.gc_asf(abi.GC_U8, FAKE, FAKE + 1, sh, 1, None) == abi.GC_ERR_ALIAS
     assert abi.gc_asf(abi.GC_U8, FAKE, FAKE + (1 << 20), sh, -2, None) == abi.GC_ERR_INVALID_ARG
     assert abi.gc_asf(abi.GC_U8, None, None, shape(0, 0, 0), 2, None) == abi.GC_OK
+
+
+def test_validate_values_validation():
+    v = abi.gc_validate_values
+    sh = shape(16, 8, 16)
+    assert v(abi.GC_F32, None, sh, 1, None) == abi.GC_ERR_INVALID_ARG
+    assert "null" in abi.last_error()
+    assert v(9, FAKE, sh, 1, None) == abi.GC_ERR_INVALID_ARG
+    assert v(abi.GC_F64, FAKE, shape(16, 8, 15), 0, None) == abi.GC_ERR_INVALID_ARG   # pitch < width
+    # nothing to scan: u8 holds no NaN or infinity, empty images hold nothing
+    assert v(abi.GC_U8, FAKE, sh, 0, None) == abi.GC_OK
+    assert v(abi.GC_F32, None, shape(0, 5, 0), 0, None) == abi.GC_OK
