@@ -328,3 +328,16 @@ def test_random_configurations(case):
         rref, rsteps, rconv = oracle.reconstruct(op, f, m)
         assert conv and rconv and steps == rsteps, what
         assert_same(host(r), rref, what + " reconstruction")
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.float64])
+@pytest.mark.parametrize("shape", [(128, 128), (128, 8192), (8192, 128)])
+def test_paper_shapes_512_erosions(dtype, shape):
+    """The square, width-varied and height-varied images of the paper's
+    second evaluation (Section 4, Table 4: 128 rows with up to 8192 columns,
+    and the transpose) with its 512-erosion chain, plain and geodesic.  At
+    8192 columns the u8 plain chain takes the separable large-window path,
+    while the f64 line no longer fits its LDS buffer and runs as a chain."""
+    f, m = rand_pair(shape, dtype, seed=shape[1] // 64 + 5)
+    assert_same(gpu_plain(oracle.ERODE, f, 512), oracle.chain(oracle.ERODE, f, 512), f"plain {shape}")
+    assert_same(gpu_chain(oracle.ERODE, f, m, 512), oracle.chain(oracle.ERODE, f, 512, m), f"geodesic {shape}")
