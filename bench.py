@@ -213,6 +213,13 @@ def verify(S, N, F, M, f, m, headline_ref, dev, with_extra=True, batch_outs=None
         for n in (13, 91, 183):
             ok[f"plain_dilation_{name}_{n}"] = bool(np.array_equal(host(gc.dilate_chain(X, n)),
                                                                    oracle.chain(oracle.DILATE, x, n)))
+        ref = oracle.chain(oracle.ERODE, x, 512)
+        ok[f"plain_erosion_{name}_512"] = bool(np.array_equal(host(gc.erode_chain(X, 512)), ref))
+        gc.set_window_path(-1)
+        try:
+            ok[f"plain_erosion_{name}_512_step_by_step"] = bool(np.array_equal(host(gc.erode_chain(X, 512)), ref))
+        finally:
+            gc.set_window_path(0)
     if batch_outs:
         items = workloads.batch_u8().items
         ok["batched_64_uneven_u8_every_16th"] = all(
@@ -446,6 +453,22 @@ def main():
                 ms_p = timed(lambda: gc.dilate_chain(x, n, out=y), max(5, args.steps), 2)
                 extra[f"plain_dilation_{dt_name}_{n}"] = {
                     "gpx_steps_per_s": round(px * n / ms_p / 1e6, 2), "ms": round(ms_p, 4)}
+            # The paper's first evaluation (its Table 4): a chain of 512 plain
+            # erosions on 1024^2, best time per dtype on its 2 x 16-core
+            # Xeon (64 threads): char 2.6 ms, float 8.2, double 17.3.  Timed
+            # through the library's default path (one separable window) and
+            # step by step (window path off).
+            ms_w = timed(lambda: gc.erode_chain(x, 512, out=y), max(5, args.steps), 2)
+            gc.set_window_path(-1)
+            try:
+                ms_s = timed(lambda: gc.erode_chain(x, 512, out=y), max(5, args.steps // 2), 2)
+            finally:
+                gc.set_window_path(0)
+            extra[f"plain_erosion_{dt_name}_512"] = {
+                "ms": round(ms_w, 4), "gpx_steps_per_s": round(px * 512 / ms_w / 1e6, 2),
+                "ms_step_by_step": round(ms_s, 4),
+                "gpx_steps_per_s_step_by_step": round(px * 512 / ms_s / 1e6, 2),
+                "paper_best_ms": {"u8": 2.6, "f32": 8.2, "f64": 17.3}[dt_name]}
 
     line = {
         "metric": "Gpixel-steps/s, 1024² u8 1500-step geodesic chain; batched & fwd+bwd vs plain",
