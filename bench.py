@@ -379,6 +379,14 @@ def main():
         ms_a = timed(lambda: gc.asf(fo, 11, out=oo), max(3, args.steps // 4), 1)
         ops_extra["asf_11"] = {"chain_steps": 264, "ms": round(ms_a, 4),
                                "gpx_steps_per_s": round(px * 264 / ms_a / 1e6, 2)}
+        # Context: the paper's best time for each operator (its Table 5:
+        # char, its 1024^2 test image, best of its systems, 64 threads) with
+        # the average chain length it reports; the image and parameters
+        # differ, so the chain lengths do too.
+        for name, paper_ms, paper_len in (("hmax_40", 7.9, 667), ("dome_40", 9.3, 668), ("hfill", 7.4, 853),
+                                          ("raobj", 15.4, 1649), ("open_rec_75", 17.2, 1693), ("qdt", 7.4, 1140),
+                                          ("pattern_spectrum_0_11", 2.8, 77), ("asf_11", 1.6, 264)):
+            ops_extra[name]["paper_best"] = {"ms": paper_ms, "avg_chain_length": paper_len}
         extra["operators_1024_u8"] = ops_extra
         del fo, oo
         # Batched: 64 uneven images in one persistent graph-recorded launch.
