@@ -262,8 +262,6 @@ __device__ __forceinline__ uint32_t qdt_erode_body_pk(const QdtArgs &qa, int rx0
     uint8_t *dst = static_cast<uint8_t *>(a.dst);
     const int k = a.k;
     const int halo = a.halo;
-    constexpr int RX = 64 * CW;
-    constexpr int RY = NW * RPW;
     constexpr uint32_t NEUTRAL = 255u;  // never wins a minimum
 
     uint32_t v[H][CW];
