@@ -943,13 +943,26 @@ __device__ __forceinline__ uint32_t chain_block_dispatch(
     }
 }
 
+// Tile of a workgroup.  Workgroups are dealt round-robin to the 8 XCDs
+// (workgroup b runs on XCD b mod 8), each with its own L2.  XCD x gets the
+// band of n/8 consecutive tiles [x n/8, (x+1) n/8): whole tile rows when the
+// rows divide evenly, so a tile's left, right and (within the band) upper
+// and lower neighbours, whose regions overlap its own, load through the
+// same L2.  Measured at 1024^2 u8: 1880 Gpx-steps/s against 1780 in raster
+// order, 1800 for 4 x 2 blocks of the tile grid and 1800 for every eighth
+// tile row per XCD.  Raster order when n is not a multiple of 8.
+__device__ __forceinline__ int xcd_tile(unsigned b, unsigned n) {
+    if ((n & 7u) != 0) return (int)b;
+    return (int)(b & 7u) * (int)(n >> 3) + (int)(b >> 3);
+}
+
 template <typename T, int OP, int MODE, bool DETECT, int CW, int RPW, int NW, int G = 1>
 __global__ __launch_bounds__(64 * NW) void chain_block_kernel(BlockArgs a) {
     if (DETECT && a.prev_word != nullptr) {
         // The image stopped changing in an earlier launch: nothing to do.
         if (*a.prev_word != a.prev_full) return;
     }
-    const int tile = blockIdx.x;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = tile % a.tiles_x;
     const int ty = tile / a.tiles_x;
     const int rx0 = tx * a.core_x - a.halo;
