@@ -91,11 +91,15 @@ __global__ __launch_bounds__(64 * NW) void persistent_chain_kernel(PersistentArg
     __shared__ __attribute__((aligned(16))) R xch[2][NW][2 * G][lanes_per_group<G>() * CW];
 
     const int tid = threadIdx.x;
-    // Items are dealt round-robin: workgroup g takes g, g + G, g + 2G, ...
-    // in list order, so no shared counter is needed.  Progress: the earliest
-    // unfinished item's dependencies are all finished, and its workgroup has
-    // finished every earlier item of its own, so it is working on it.
-    for (int it = blockIdx.x; it < a.n_items; it += gridDim.x) {
+    // Items are dealt round-robin over workgroup labels: the workgroup with
+    // label g takes items g, g + G, g + 2G, ... in list order, so no shared
+    // counter is needed.  Labels go XCD by XCD (xcd_tile), so runs of
+    // consecutive items, i.e. neighbouring tiles of one image, run on one
+    // XCD and share its L2.  Progress: the earliest unfinished item's
+    // dependencies are all finished, and its workgroup has finished every
+    // earlier item of its own, so it is working on it.
+    const int first = xcd_tile(blockIdx.x, gridDim.x);
+    for (int it = first; it < a.n_items; it += gridDim.x) {
         const PlanItem item = a.items[it];
         const PlanImage &im = a.images[item.image];
         const int tx = item.tile % im.tiles_x;
