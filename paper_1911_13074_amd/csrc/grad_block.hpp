@@ -49,6 +49,19 @@ namespace geochain {
 constexpr uint8_t CODE_MASK = 9;
 constexpr uint8_t CODE_NONE = 255;
 
+// Block of a workgroup: the grid (column tile, row tile, image) is relabelled
+// XCD by XCD (xcd_tile), so neighbouring tiles, whose regions overlap, run
+// on one XCD and share its L2.
+struct GradBlock {
+    int bx, by, img;
+};
+__device__ __forceinline__ GradBlock grad_block() {
+    const unsigned gx = gridDim.x, gy = gridDim.y;
+    const unsigned lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const unsigned t = (unsigned)xcd_tile(lin, gx * gy * gridDim.z);
+    return GradBlock{(int)(t % gx), (int)((t / gx) % gy), (int)(t / (gx * gy))};
+}
+
 template <int OP, typename T>
 __device__ __forceinline__ bool better(T a, T b) {
     return OP == OP_DILATE ? (a > b) : (a < b);
@@ -162,12 +175,13 @@ __global__ __launch_bounds__(GradTile<T>::THREADS, GradTile<T>::CODES_WAVES_PER_
     __shared__ T xv[2][NW][2][GB_RW];        // edge rows' row-pass values
     __shared__ uint8_t xi[2][NW][2][GB_RW];  // and their dx indices
     __shared__ __attribute__((aligned(16))) uint8_t sc[2][CY][GB_CX];
-    const int img = blockIdx.z;
+    const GradBlock blk = grad_block();
+    const int img = blk.img;
     const T *src = static_cast<const T *>(a.src) + img * a.image_stride;
     const T *msk = static_cast<const T *>(a.mask) + img * a.image_stride;
     T *dst = static_cast<T *>(a.dst) + img * a.image_stride;
     uint8_t *codes = a.codes + img * a.codes_image;
-    const int x0 = blockIdx.x * GB_CX, y0 = blockIdx.y * CY;  // core origin
+    const int x0 = blk.bx * GB_CX, y0 = blk.by * CY;  // core origin
     const int rx0 = x0 - GB_K, ry0 = y0 - GB_K;               // region origin
     const int x = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -258,12 +272,13 @@ __global__ __launch_bounds__(GradTile<T>::THREADS) void block_bwd_kernel(GradBlo
     constexpr int RH = G::RH, CY = G::CY, NW = G::NW;
     __shared__ __attribute__((aligned(16))) uint8_t scd[GB_K][RH][GB_RW];
     __shared__ T xg[2][NW][2][GB_RW];
-    const int img = blockIdx.z;
+    const GradBlock blk = grad_block();
+    const int img = blk.img;
     const T *gin = static_cast<const T *>(a.src) + img * a.image_stride;
     T *gout = static_cast<T *>(a.dst) + img * a.image_stride;
     T *gm = static_cast<T *>(a.g_mask) + img * a.image_stride;
     const uint8_t *codes = a.codes + img * a.codes_image;
-    const int x0 = blockIdx.x * GB_CX, y0 = blockIdx.y * CY;
+    const int x0 = blk.bx * GB_CX, y0 = blk.by * CY;
     const int rx0 = x0 - GB_K, ry0 = y0 - GB_K;
     const int x = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
