@@ -195,7 +195,8 @@ struct Workspace {
     void *buf = nullptr;
     size_t bytes = 0;
     uint32_t *words = nullptr;      // device change words
-    uint32_t *host_words = nullptr; // pinned mirror
+    uint32_t *host_words = nullptr; // pinned, mapped mirror (host address)
+    uint32_t *host_words_dev = nullptr; // the same memory as the device sees it
     size_t nwords = 0;
     void *partials = nullptr;       // PARTIALS_MAX per-workgroup extrema (operators)
     void *buf2 = nullptr;           // images of composed operators (granulometry)
@@ -230,16 +231,19 @@ static int get_workspace(void *stream, size_t bytes, size_t nwords, Workspace **
             GC_HIP(hipHostFree(w.host_words));
             w.words = nullptr;
             w.host_words = nullptr;
+            w.host_words_dev = nullptr;
             w.nwords = 0;
         }
         if (hipMalloc((void **)&w.words, nwords * 4) != hipSuccess) {
             (void)hipGetLastError();
             return fail(GC_ERR_NO_MEMORY, "change words");
         }
-        if (hipHostMalloc((void **)&w.host_words, nwords * 4, hipHostMallocDefault) != hipSuccess) {
+        if (hipHostMalloc((void **)&w.host_words, nwords * 4, hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess) {
             (void)hipGetLastError();
             return fail(GC_ERR_NO_MEMORY, "pinned change words");
         }
+        GC_HIP(hipHostGetDevicePointer((void **)&w.host_words_dev, w.host_words, 0));
         w.nwords = nwords;
     }
     *out = &w;
@@ -290,6 +294,22 @@ static int get_buf2(void *stream, size_t bytes, void **out) {
 __global__ void fill_words_kernel(uint32_t *p, int n, uint32_t v) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// Copies n device words into the mapped host mirror with system-scope
+// stores: after the stream has been synchronised the host reads them
+// directly, with no copy command.
+__global__ void publish_words_kernel(const uint32_t *src, uint32_t *host_dst, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        __hip_atomic_store(host_dst + i, src[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// The first n change words, read on the host (synchronises the stream).
+static int read_words(Workspace *ws, int n, hipStream_t st) {
+    hipLaunchKernelGGL(publish_words_kernel, dim3(1), dim3(64), 0, st, ws->words, ws->host_words_dev, n);
+    GC_HIP(hipGetLastError());
+    GC_HIP(hipStreamSynchronize(st));
+    return GC_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -696,8 +716,10 @@ static int run_reconstruct(gc_dtype dtype, int op, const void *marker, const voi
             cur = dst;
             ++blocks;
         }
-        GC_HIP(hipMemcpyAsync(ws->host_words, ws->words, G * 4, hipMemcpyDeviceToHost, st));
-        GC_HIP(hipStreamSynchronize(st));
+        {
+            const int wrc = read_words(ws, G, st);
+            if (wrc != GC_OK) return wrc;
+        }
         for (int j = 0; j < G; ++j) {
             const uint32_t full = (uint32_t)((1ull << ks[j]) - 1);
             const uint32_t wrd = ws->host_words[j];
@@ -722,8 +744,10 @@ static int run_reconstruct(gc_dtype dtype, int op, const void *marker, const voi
         auto ag = make_args(result, dst, 1, ws->words, nullptr, 0u);
         fn(ag.first, ag.second, st);
         GC_HIP(hipGetLastError());
-        GC_HIP(hipMemcpyAsync(ws->host_words, ws->words, 4, hipMemcpyDeviceToHost, st));
-        GC_HIP(hipStreamSynchronize(st));
+        {
+            const int wrc = read_words(ws, 1, st);
+            if (wrc != GC_OK) return wrc;
+        }
         converged = ws->host_words[0] == 0;
         // result still names the chain of max_steps steps (dst equals it if
         // converged, and is one step further otherwise).
@@ -982,8 +1006,10 @@ static int run_qdt_phase(const QdtLayout &L, const gc_shape &s, const void *src0
             cur = dst;
             ++launched;
         }
-        GC_HIP(hipMemcpyAsync(ws->host_words, ws->words, group * 4, hipMemcpyDeviceToHost, st));
-        GC_HIP(hipStreamSynchronize(st));
+        {
+            const int wrc = read_words(ws, group, st);
+            if (wrc != GC_OK) return wrc;
+        }
         for (int j = 0; j < group; ++j) {
             const uint32_t wrd = ws->host_words[j];
             *result = dsts[j];
@@ -1624,8 +1650,10 @@ static int run_value_scan_t(const T *img, const gc_shape &s, uint32_t *found, vo
     else
         hipLaunchKernelGGL((value_scan_kernel<T, false>), dim3(grid), dim3(PX_THREADS), 0, st, p, ws->words);
     GC_HIP(hipGetLastError());
-    GC_HIP(hipMemcpyAsync(ws->host_words, ws->words, 4, hipMemcpyDeviceToHost, st));
-    GC_HIP(hipStreamSynchronize(st));
+    {
+        const int wrc = read_words(ws, 1, st);
+        if (wrc != GC_OK) return wrc;
+    }
     *found = ws->host_words[0];
     return GC_OK;
 }
