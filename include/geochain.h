@@ -36,6 +36,8 @@
  *     gc_plan objects.
  *   - shape.pitch is in elements and must be >= shape.width; marker, mask
  *     and out share the shape.  width or height 0 is a valid empty image.
+ *     Sides above 2^25 or more than 2^36 pixels are GC_ERR_UNSUPPORTED
+ *     (2^36 u8 pixels are 64 GiB per image).
  *   - out may equal marker (in place, as the paper's filters run in place,
  *     Section 3.3).  out must not overlap mask (GC_ERR_ALIAS), and a partial
  *     overlap of out with marker is rejected too.
@@ -235,7 +237,8 @@ int gc_quasi_distance(gc_dtype dtype, const void *f, int32_t *dist, void *residu
  * workspace (two work images per item plus counters) and records the launch
  * into a HIP graph.  It copies the gc_item array; the images themselves
  * must stay allocated while the plan is used.  It synchronises the device
- * stream it uses for recording.
+ * stream it uses for recording.  A plan whose work list (tiles x blocks
+ * summed over the items) exceeds 2^31 - 1 is GC_ERR_UNSUPPORTED.
  *
  * gc_plan_launch replays the graph on hip_stream (asynchronous).  Launches
  * of one plan must not overlap each other (they share the workspace).

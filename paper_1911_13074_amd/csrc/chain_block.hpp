@@ -164,6 +164,7 @@ struct BlockArgs {
     int32_t halo;          // offset of the core inside the region
     int32_t core_x, core_y;
     int32_t tiles_x;
+    int32_t tile0;         // tile of the launch's first workgroup (large images take several launches)
     uint32_t *change_word;       // reconstruction: OR of per-step change bits
     const uint32_t *prev_word;   // reconstruction: predecessor's word (or null)
     uint32_t prev_full;          // value prev_word holds if every step changed
@@ -962,7 +963,7 @@ __global__ __launch_bounds__(64 * NW) void chain_block_kernel(BlockArgs a) {
         // The image stopped changing in an earlier launch: nothing to do.
         if (*a.prev_word != a.prev_full) return;
     }
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = a.tile0 + xcd_tile(blockIdx.x, gridDim.x);
     const int tx = tile % a.tiles_x;
     const int ty = tile / a.tiles_x;
     const int rx0 = tx * a.core_x - a.halo;

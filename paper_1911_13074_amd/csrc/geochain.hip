@@ -75,8 +75,15 @@ static int validate_shape(gc_dtype dtype, const gc_shape &s) {
     if (s.width < 0 || s.height < 0) return fail(GC_ERR_INVALID_ARG, "negative image size");
     if (s.pitch < s.width) return fail(GC_ERR_INVALID_ARG, "pitch %lld < width %lld",
                                        (long long)s.pitch, (long long)s.width);
-    if (s.width > (1 << 30) || s.height > (1 << 30))
-        return fail(GC_ERR_UNSUPPORTED, "image sides above 2^30 are not supported");
+    // Sides up to 2^25 keep every launch below 2^32 work-items (the line
+    // kernels of the large-window path run one 64-lane workgroup per image
+    // line); 2^36 pixels (a 64 GiB u8 image) keep tile counts in 32 bits.
+    if (s.width > (int64_t(1) << 25) || s.height > (int64_t(1) << 25))
+        return fail(GC_ERR_UNSUPPORTED, "image sides above 2^25 are not supported (%lld x %lld)",
+                    (long long)s.width, (long long)s.height);
+    if (s.width * s.height > (int64_t(1) << 36))
+        return fail(GC_ERR_UNSUPPORTED, "images above 2^36 pixels are not supported (%lld x %lld)",
+                    (long long)s.width, (long long)s.height);
     return GC_OK;
 }
 
@@ -365,11 +372,22 @@ static void prof_end(int idx, hipStream_t st) {
 // ---------------------------------------------------------------------------
 using LaunchFn = void (*)(const BlockArgs &, int grid, hipStream_t);
 
+// One workgroup per tile.  A grid holds fewer than 2^32 work-items, so the
+// tiles of a large image go out in launches of at most MAX_TILES_PER_LAUNCH
+// (2^30 work-items), each told its first tile.  The tiles of one block of
+// steps are independent (they read src and write disjoint cores of dst), so
+// consecutive launches on the stream compute exactly what one would.
+constexpr int MAX_TILES_PER_LAUNCH = 1 << 20;
+
 template <typename T, int OP, int MODE, bool DETECT, int FAM>
 static void launch_block(const BlockArgs &a, int grid, hipStream_t st) {
     using F = Family<T, FAM>;
-    hipLaunchKernelGGL((chain_block_kernel<T, OP, MODE, DETECT, F::CW, F::RPW, F::NW, F::G>),
-                       dim3(grid), dim3(64 * F::NW), 0, st, a);
+    for (int t0 = 0; t0 < grid; t0 += MAX_TILES_PER_LAUNCH) {
+        BlockArgs b = a;
+        b.tile0 = t0;
+        hipLaunchKernelGGL((chain_block_kernel<T, OP, MODE, DETECT, F::CW, F::RPW, F::NW, F::G>),
+                           dim3(std::min(grid - t0, MAX_TILES_PER_LAUNCH)), dim3(64 * F::NW), 0, st, b);
+    }
 }
 
 template <typename T, int OP, int MODE, bool DETECT>
@@ -938,7 +956,13 @@ static int run_asf(gc_dtype dtype, const void *f, void *out, const gc_shape &s, 
 // ---------------------------------------------------------------------------
 template <typename T, int PHASE, int CW, int RPW, int NW>
 static void launch_qdt(const QdtArgs &qa, int grid, hipStream_t st) {
-    hipLaunchKernelGGL((qdt_block_kernel<T, PHASE, CW, RPW, NW>), dim3(grid), dim3(64 * NW), 0, st, qa);
+    // split like launch_block: the cores of r and d a tile updates are its own
+    for (int t0 = 0; t0 < grid; t0 += MAX_TILES_PER_LAUNCH) {
+        QdtArgs q = qa;
+        q.b.tile0 = t0;
+        hipLaunchKernelGGL((qdt_block_kernel<T, PHASE, CW, RPW, NW>), dim3(std::min(grid - t0, MAX_TILES_PER_LAUNCH)),
+                           dim3(64 * NW), 0, st, q);
+    }
 }
 
 struct QdtLayout {
@@ -1290,7 +1314,7 @@ static int plan_build(gc_dtype dtype, int op, const gc_item *items, int32_t n_it
     std::vector<int> img_of_item;  // plan image index -> gc_item index
     size_t ws_bytes = 0;
     std::vector<size_t> ws_off;
-    int32_t flags = 0;
+    int64_t flags = 0;  // per-tile counters; at most the item count, checked below
     std::vector<std::pair<int, int>> copies;  // (gc_item index, kind) 0: n=0 copy, 1: marker->ws1
     for (int32_t i = 0; i < n_items; ++i) {
         const gc_item &it = p->items[i];
@@ -1310,8 +1334,8 @@ static int plan_build(gc_dtype dtype, int op, const gc_item *items, int32_t n_it
         im.tiles_x = (int32_t)((it.shape.width + im.core_x - 1) / im.core_x);
         im.tiles_y = (int32_t)((it.shape.height + im.core_y - 1) / im.core_y);
         im.blocks = (int32_t)((it.n_steps + im.k - 1) / im.k);
-        im.flag_base = flags;
-        flags += im.tiles_x * im.tiles_y;
+        im.flag_base = (int32_t)std::min<int64_t>(flags, INT32_MAX);
+        flags += (int64_t)im.tiles_x * im.tiles_y;
         im.src0_ws1 = (it.out == it.marker && im.blocks == 1) ? 1 : 0;
         if (im.src0_ws1) copies.push_back({i, 1});
         const size_t bytes = (size_t)((it.shape.height - 1) * it.shape.pitch + it.shape.width) * es;
@@ -1331,7 +1355,15 @@ static int plan_build(gc_dtype dtype, int op, const gc_item *items, int32_t n_it
     });
     int max_blocks = 0;
     for (auto &im : imgs) max_blocks = std::max(max_blocks, im.blocks);
+    int64_t total_items = 0;
+    for (auto &im : imgs) total_items += (int64_t)im.tiles_x * im.tiles_y * im.blocks;
+    if (total_items > INT32_MAX) {
+        plan_free(p);
+        return fail(GC_ERR_UNSUPPORTED, "a plan of %lld work items (tiles x blocks) exceeds 2^31 - 1",
+                    (long long)total_items);
+    }
     std::vector<PlanItem> plan_items;
+    plan_items.reserve((size_t)total_items);
     for (int b = 0; b < max_blocks; ++b)
         for (int j : order) {
             if (b >= imgs[j].blocks) continue;

@@ -445,7 +445,7 @@ __global__ __launch_bounds__(64 * NW) void qdt_block_kernel(QdtArgs qa) {
         // an earlier launch already saw a step without change
         if (*a.prev_word != a.prev_full) return;
     }
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = a.tile0 + xcd_tile(blockIdx.x, gridDim.x);
     const int rx0 = (tile % a.tiles_x) * a.core_x - a.halo;
     const int ry0 = (tile / a.tiles_x) * a.core_y - a.halo;
     using R = typename QdtReg<T>::type;

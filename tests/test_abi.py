@@ -70,6 +70,21 @@ def test_invalid_arguments(call):
     assert abi.last_error() != ""
 
 
+def test_size_limits():
+    """Sides above 2^25 and images above 2^36 pixels are refused before any
+    HIP call (launch grids and tile counts stay within 32 bits)."""
+    steps = ctypes.c_int64()
+    for s in (shape((1 << 25) + 1, 1, (1 << 25) + 1), shape(1, (1 << 25) + 1, 1),
+              shape(1 << 20, (1 << 16) + 1, 1 << 20)):
+        far = 1 << 46
+        assert abi.gc_geodesic_dilate_chain(abi.GC_U8, FAKE, FAKE + far, FAKE + 2 * far, s, 3,
+                                            None) == abi.GC_ERR_UNSUPPORTED
+        assert abi.gc_erode_chain(abi.GC_F32, FAKE, FAKE + far, s, 3, None) == abi.GC_ERR_UNSUPPORTED
+        assert abi.gc_reconstruct_by_dilation(abi.GC_U8, FAKE, FAKE + far, FAKE + 2 * far, s, -1,
+                                              ctypes.byref(steps), None) == abi.GC_ERR_UNSUPPORTED
+        assert "not supported" in abi.last_error()
+
+
 def test_aliasing_is_rejected():
     s = shape(100, 100, 128)
     # out == mask

@@ -9,6 +9,8 @@ shape (steps per launch and tile family), reconstruction step counts, the
 step cap, and the full-size 1024x1024 workloads in the launch configuration
 the benchmark times.
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -289,6 +291,61 @@ def test_image_beyond_2_31_pixels_sampled():
         assert int(out[y, x]) == int(ref), (y, x)
     del F, M, out
     torch.cuda.empty_cache()
+
+
+def test_image_beyond_one_launch_grid():
+    """131172 x 131035 u8 (1.7e10 pixels, 16 GiB per image) with 32 geodesic
+    dilations: one block of 64 x 64 cores is 2050 x 2048 = 4,198,400 tiles,
+    more workgroups than one grid of 2^32 work-items holds, so the block goes
+    out as five launches (four of 2^20 tiles and one of 4096).  The oracle on
+    crops checks the pixels on both sides of every launch boundary, the
+    corners and random pixels; the 8-wave family (other code, the same
+    split) must give the same whole image."""
+    W, H, n = 131172, 131035, 32
+    gen = torch.Generator(device="cuda").manual_seed(23)
+    F = torch.randint(0, 200, (H, W), dtype=torch.uint8, device="cuda", generator=gen)
+    M = torch.randint(50, 256, (H, W), dtype=torch.uint8, device="cuda", generator=gen)
+    out = gc.geodesic_dilate_chain(F, M, n)
+    torch.cuda.synchronize()
+    core, tiles_x = 64, (W + 63) // 64
+    pts = [(0, 0), (0, W - 1), (H - 1, 0), (H - 1, W - 1), (H // 2, W - 1), (H - 1, W // 2)]
+    for t0 in (1 << 20, 2 << 20, 3 << 20, 4 << 20):
+        ty, tx = divmod(t0, tiles_x)            # first core pixel of the launch
+        pts.append((ty * core, tx * core))
+        ty, tx = divmod(t0 - 1, tiles_x)        # last core pixel of the one before
+        pts.append((min(H - 1, ty * core + core - 1), min(W - 1, tx * core + core - 1)))
+    rng = np.random.default_rng(29)
+    pts += [(int(rng.integers(0, H)), int(rng.integers(0, W))) for _ in range(24)]
+    for y, x in pts:
+        y0, y1 = max(0, y - n), min(H, y + n + 1)
+        x0, x1 = max(0, x - n), min(W, x + n + 1)
+        f = F[y0:y1, x0:x1].cpu().numpy()
+        m = M[y0:y1, x0:x1].cpu().numpy()
+        ref = oracle.chain(oracle.DILATE, f, n, m)[y - y0, x - x0]
+        assert int(out[y, x]) == int(ref), (y, x)
+    gc.set_tuning(n, 0)   # 128 x 128 regions of 8 waves x 16 rows, same 64 x 64 cores
+    out2 = gc.geodesic_dilate_chain(F, M, n)
+    gc.set_tuning(0, -1)
+    assert torch.equal(out, out2)
+    del F, M, out, out2
+    torch.cuda.empty_cache()
+
+
+def test_plan_beyond_2_31_work_items_is_rejected():
+    """A plan whose work list would not fit 32-bit item indices is refused
+    before anything is allocated or launched (the image pointers are never
+    dereferenced)."""
+    fake = 1 << 44
+    arr = (abi.gc_item * 1)()
+    arr[0].marker = fake
+    arr[0].mask = fake + (1 << 37)
+    arr[0].out = fake + (2 << 37)
+    arr[0].shape = abi.gc_shape(1 << 18, 1 << 18, 1 << 18)
+    arr[0].n_steps = 1 << 20
+    handle = ctypes.c_void_p()
+    assert abi.gc_plan_create(abi.GC_U8, abi.GC_DILATE, arr, 1, ctypes.byref(handle)) == abi.GC_ERR_UNSUPPORTED
+    assert "work items" in abi.last_error()
+    assert not handle.value
 
 
 # --------------------------------------------------------------------------
