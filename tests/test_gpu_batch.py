@@ -195,3 +195,37 @@ def test_tuned_plan_matches_and_leaves_inputs_alone():
     for out, ref in zip(outs, refs):
         assert np.array_equal(out.cpu().numpy(), ref)
     plan.close()
+
+
+def test_plan_with_image_beyond_one_launch_grid():
+    """A plan that mixes a 131172 x 131035 u8 image (1.7e10 pixels: 1491 x
+    1489 tiles of 88 x 88 cores per block of 20 steps, 4.4 million work items
+    over its two blocks) with a small image.  After n steps a pixel depends
+    only on the marker and mask within chessboard distance n, so the oracle
+    on crops checks sampled pixels of the large output; the small one is
+    checked whole."""
+    W, H, n = 131172, 131035, 40
+    gen = torch.Generator(device="cuda").manual_seed(31)
+    F = torch.randint(0, 200, (H, W), dtype=torch.uint8, device="cuda", generator=gen)
+    M = torch.randint(50, 256, (H, W), dtype=torch.uint8, device="cuda", generator=gen)
+    rng = np.random.default_rng(37)
+    f2, m2 = rand_img((300, 411), np.uint8, rng), rand_img((300, 411), np.uint8, rng)
+    plan = gc.BatchPlan("dilate", [(F, M, n), (dev(f2), dev(m2), 57)])
+    try:
+        assert plan.info()["work_items"] > 4_000_000
+        plan.launch()
+        plan.status()
+        out = plan.outs[0]
+        torch.cuda.synchronize()
+        pts = [(0, 0), (0, W - 1), (H - 1, 0), (H - 1, W - 1), (H // 2, W // 2)]
+        pts += [(int(rng.integers(0, H)), int(rng.integers(0, W))) for _ in range(30)]
+        for y, x in pts:
+            y0, y1 = max(0, y - n), min(H, y + n + 1)
+            x0, x1 = max(0, x - n), min(W, x + n + 1)
+            ref = oracle.chain(oracle.DILATE, F[y0:y1, x0:x1].cpu().numpy(), n, M[y0:y1, x0:x1].cpu().numpy())
+            assert int(out[y, x]) == int(ref[y - y0, x - x0]), (y, x)
+        assert np.array_equal(host(plan.outs[1]), oracle.chain(oracle.DILATE, f2, 57, m2))
+    finally:
+        plan.close()
+    del F, M, plan
+    torch.cuda.empty_cache()
