@@ -1303,7 +1303,11 @@ static int plan_build(gc_dtype dtype, int op, const gc_item *items, int32_t n_it
     p->op = op;
     p->mode = mode;
     p->items.assign(items, items + n_items);
-    GC_HIP(hipGetDevice(&p->device));
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        (void)hipGetLastError();
+        plan_free(p);
+        return fail(GC_ERR_HIP, "hipGetDevice failed");
+    }
 
     const PlanChoice choice = forced ? *forced : choose_plan_batch(dtype, op, mode, p->items);
     p->fam = choice.fam;
@@ -1456,18 +1460,19 @@ static int plan_build(gc_dtype dtype, int op, const gc_item *items, int32_t n_it
 
 static int plan_time(gc_plan *p, int reps, double *ms_out) {
     hipStream_t st = p->cap_stream;
-    hipEvent_t a, b;
-    GC_HIP(hipEventCreate(&a));
-    GC_HIP(hipEventCreate(&b));
-    GC_HIP(hipGraphLaunch(p->exec, st));  // warm-up
-    GC_HIP(hipEventRecord(a, st));
-    for (int i = 0; i < reps; ++i) GC_HIP(hipGraphLaunch(p->exec, st));
-    GC_HIP(hipEventRecord(b, st));
-    GC_HIP(hipEventSynchronize(b));
+    hipEvent_t a = nullptr, b = nullptr;
     float ms = 0;
-    GC_HIP(hipEventElapsedTime(&ms, a, b));
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = hipGraphLaunch(p->exec, st);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(a, st);
+    for (int i = 0; i < reps && e == hipSuccess; ++i) e = hipGraphLaunch(p->exec, st);
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (e != hipSuccess) return fail(GC_ERR_HIP, "timing a plan failed: %s", hipGetErrorString(e));
     *ms_out = ms / reps;
     return *p->error_h ? fail(GC_ERR_HIP, "dependency wait hit its bound while tuning") : GC_OK;
 }
