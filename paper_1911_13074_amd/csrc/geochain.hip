@@ -1488,7 +1488,11 @@ static int autotune(gc_dtype dtype, int op, int geodesic, int64_t width, int64_t
         (void)hipGetLastError();
         return fail(GC_ERR_NO_MEMORY, "autotune scratch");
     }
-    GC_HIP(hipMemset(buf, 0, std::max<size_t>(bytes, 1) * 3 * copies));
+    if (hipMemset(buf, 0, std::max<size_t>(bytes, 1) * 3 * copies) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(buf);
+        return fail(GC_ERR_HIP, "autotune scratch clear failed");
+    }
     const int n_steps = 240;
     TuneVal tv;
     double best_rate = 0;
