@@ -34,7 +34,8 @@ class GeodesicChainFunction(torch.autograd.Function):
             cur = nxt
             if i + 1 < len(starts):
                 ckpts.append(cur.view_as(marker))
-        out = cur.view_as(marker).clone() if n_steps > 0 else marker.clone()
+        # the last segment's state is a fresh tensor that no checkpoint holds
+        out = cur.view_as(marker) if n_steps > 0 else marker.clone()
         ctx.n_steps, ctx.seg, ctx.op = n_steps, seg, op
         ctx.save_for_backward(mask, *ckpts)
         return out
