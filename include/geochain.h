@@ -48,6 +48,12 @@
  *     gc_last_error() gives a detail message for the calling thread.
  *   - Calls that run concurrently on different streams are safe; each
  *     (device, stream) pair has its own workspace.
+ *   - The chain entry points (geodesic and plain) may be recorded into a
+ *     HIP graph by stream capture once a call of at least the same size has
+ *     run on the capturing stream (that call sizes the stream's workspace;
+ *     a capture that would have to grow it fails).  Entry points that read
+ *     a convergence word on the host (reconstructions, the operators built
+ *     on them, the quasi-distance transform) cannot be captured.
  */
 #ifndef GEOCHAIN_H
 #define GEOCHAIN_H

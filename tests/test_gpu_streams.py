@@ -2,7 +2,8 @@
 chains, reconstructions and plain chains issued at the same time from
 several host threads, each on its own stream, give exactly what the same
 calls give one after another on the default stream (which the oracle
-checks for the first input)."""
+checks for the first input).  Chains also record into a HIP graph once a
+first call on the capturing stream has sized its workspace."""
 import threading
 
 import numpy as np
@@ -66,3 +67,35 @@ def test_calls_from_threads_on_their_own_streams():
         for a, r, s, c, e in outs:
             assert torch.equal(a, a0) and torch.equal(e, e0), i
             assert c and c0 and s == s0 and torch.equal(r, r0), i
+
+
+def test_chains_captured_in_a_graph_replay_exactly():
+    """Geodesic and plain chains (several launches each, ping-pong through
+    the stream's workspace) captured after a warm-up call on the capturing
+    stream; every replay, with eager library work and synchronisation
+    between replays, equals the eager result, which the oracle checks."""
+    f, m = inputs(41, (517, 389))
+    F, M = torch.from_numpy(f).cuda(), torch.from_numpy(m).cuda()
+    out_g = torch.empty_like(F)
+    out_p = torch.empty_like(F)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        gc.geodesic_dilate_chain(F, M, 100, out=out_g)
+        gc.erode_chain(F, 9, out=out_p)
+    s.synchronize()
+    ref_g, ref_p = out_g.clone(), out_p.clone()
+    assert np.array_equal(ref_g.cpu().numpy(), oracle.chain(oracle.DILATE, f, 100, m))
+    assert np.array_equal(ref_p.cpu().numpy(), oracle.chain(oracle.ERODE, f, 9))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        gc.geodesic_dilate_chain(F, M, 100, out=out_g)
+        gc.erode_chain(F, 9, out=out_p)
+    for _ in range(4):
+        out_g.zero_()
+        out_p.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out_g, ref_g) and torch.equal(out_p, ref_p)
+        gc.geodesic_erode_chain(F, M, 33)   # eager work on the default stream
+        torch.cuda.synchronize()
