@@ -267,16 +267,22 @@ def test_repeat_determinism():
 # --------------------------------------------------------------------------
 # maximum sizes: more than 2^31 pixels per image
 # --------------------------------------------------------------------------
-def test_image_beyond_2_31_pixels_sampled():
-    """46341 x 46341 u8 (2.15e9 pixels per image; element offsets beyond
-    2^31), 40 geodesic dilations.  After n steps a pixel depends only on the
-    marker and mask within chessboard distance n, so the oracle on a crop
-    reaching n pixels past it (or to the image edge) gives it exactly; 40
-    sampled pixels, corners and edges included."""
+@pytest.mark.parametrize("dtype", [torch.uint8, torch.float32])
+def test_image_beyond_2_31_pixels_sampled(dtype):
+    """46341 x 46341 u8 and f32 (2.15e9 pixels per image; element offsets
+    beyond 2^31, byte offsets beyond 2^33 for f32), 40 geodesic dilations.
+    After n steps a pixel depends only on the marker and mask within
+    chessboard distance n, so the oracle on a crop reaching n pixels past it
+    (or to the image edge) gives it exactly; 40 sampled pixels, corners and
+    edges included."""
     side, n = 46341, 40
     gen = torch.Generator(device="cuda").manual_seed(11)
-    F = torch.randint(0, 200, (side, side), dtype=torch.uint8, device="cuda", generator=gen)
-    M = torch.randint(50, 256, (side, side), dtype=torch.uint8, device="cuda", generator=gen)
+    if dtype == torch.uint8:
+        F = torch.randint(0, 200, (side, side), dtype=dtype, device="cuda", generator=gen)
+        M = torch.randint(50, 256, (side, side), dtype=dtype, device="cuda", generator=gen)
+    else:
+        F = torch.rand((side, side), dtype=dtype, device="cuda", generator=gen)
+        M = torch.rand((side, side), dtype=dtype, device="cuda", generator=gen) + 0.25
     out = gc.geodesic_dilate_chain(F, M, n)
     torch.cuda.synchronize()
     rng = np.random.default_rng(5)
@@ -288,7 +294,7 @@ def test_image_beyond_2_31_pixels_sampled():
         f = F[y0:y1, x0:x1].cpu().numpy()
         m = M[y0:y1, x0:x1].cpu().numpy()
         ref = oracle.chain(oracle.DILATE, f, n, m)[y - y0, x - x0]
-        assert int(out[y, x]) == int(ref), (y, x)
+        assert out[y, x].item() == ref.item(), (y, x)
     del F, M, out
     torch.cuda.empty_cache()
 
