@@ -235,7 +235,9 @@ int gc_quasi_distance(gc_dtype dtype, const void *f, int32_t *dist, void *residu
  * gc_item: marker / mask / out are device pointers (same rules as the
  * single-image calls: out may equal marker, must not overlap mask).  All
  * items of one plan must be geodesic (mask != NULL) or all plain (mask ==
- * NULL).  n_steps >= 0.
+ * NULL).  n_steps >= 0 runs that many steps; n_steps < 0 (geodesic items
+ * only) runs to stability, as gc_reconstruct_by_dilation / _erosion do for
+ * one image (Eq. 5).
  *
  * gc_plan_create validates the items, chooses the tile family and steps per
  * block (from the autotuner's table when it has an entry for the items'
@@ -248,14 +250,25 @@ int gc_quasi_distance(gc_dtype dtype, const void *f, int32_t *dist, void *residu
  *
  * gc_plan_launch replays the graph on hip_stream (asynchronous).  Launches
  * of one plan must not overlap each other (they share the workspace).
+ * With run-to-stability items it is synchronous instead: each replay runs
+ * every active image for 8 blocks of 20 steps while the kernel records, per
+ * block, which steps changed a pixel; between replays the host retires the
+ * images that reached a step without change (their result is then a fixed
+ * point) and the others continue from their output.  Fixed-length items
+ * finish in the first replay.  It returns GC_ERR_NOT_CONVERGED if an image
+ * exceeds width x height + 1 steps, which a reconstruction cannot.
+ *
+ * gc_plan_steps writes, per item (host array of n_items), the steps of the
+ * last launch: n_steps for fixed-length items, the number of steps that
+ * changed a pixel for run-to-stability items (-1 before the first launch).
  *
  * gc_plan_status waits for the plan's last launch and returns GC_OK, or
  * GC_ERR_HIP if a dependency wait inside the kernel hit its safety bound
  * (results then invalid).
  *
  * gc_plan_info reports totals of the plan (any pointer may be NULL):
- * pixel-steps per launch, work items, workgroups launched, tile family and
- * the largest steps-per-block used.
+ * pixel-steps per launch of the fixed-length items, work items per replay,
+ * workgroups launched, tile family and the largest steps-per-block used.
  *
  * gc_plan_tune times the kernel's launch shapes (tile family x steps per
  * block, the built-in choice among them) on scratch images with exactly
@@ -263,7 +276,8 @@ int gc_quasi_distance(gc_dtype dtype, const void *f, int32_t *dist, void *residu
  * or written, so in-place items are safe -- and rebuilds the plan with the
  * fastest.  The handle stays valid; *best_ms (host, may be NULL) receives
  * the winner's time per launch.  Synchronises; allocates scratch for three
- * images per item while it runs.
+ * images per item while it runs.  Plans with run-to-stability items keep
+ * the built-in shape (GC_ERR_UNSUPPORTED).
  * ------------------------------------------------------------------- */
 typedef struct {
     const void *marker;
@@ -279,6 +293,7 @@ int gc_plan_create(gc_dtype dtype, gc_op op, const gc_item *items, int32_t n_ite
                    gc_plan **plan_out);
 int gc_plan_launch(gc_plan *plan, void *hip_stream);
 int gc_plan_status(gc_plan *plan);
+int gc_plan_steps(const gc_plan *plan, int64_t *steps);
 int gc_plan_info(const gc_plan *plan, int64_t *px_steps, int64_t *work_items,
                  int32_t *workgroups, int32_t *tile, int32_t *block_steps);
 int gc_plan_destroy(gc_plan *plan);

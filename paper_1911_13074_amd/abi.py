@@ -70,6 +70,7 @@ SIGNATURES = {
                                       ctypes.POINTER(ctypes.c_void_p)]),
     "gc_plan_launch": (ctypes.c_int, [_VP, _VP]),
     "gc_plan_status": (ctypes.c_int, [_VP]),
+    "gc_plan_steps": (ctypes.c_int, [_VP, _P_I64]),
     "gc_plan_info": (ctypes.c_int, [_VP, _P_I64, _P_I64, ctypes.POINTER(_I32),
                                     ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "gc_plan_destroy": (ctypes.c_int, [_VP]),

@@ -1094,19 +1094,19 @@ struct PersistentFns {
     int threads;
 };
 
-template <typename T, int OP, int MODE, int FAM>
+template <typename T, int OP, int MODE, int FAM, bool DETECT = false>
 static void launch_persistent(const PersistentArgs &a, int grid, hipStream_t st) {
     using F = Family<T, FAM>;
-    hipLaunchKernelGGL((persistent_chain_kernel<T, OP, MODE, F::CW, F::RPW, F::NW, F::G>), dim3(grid),
+    hipLaunchKernelGGL((persistent_chain_kernel<T, OP, MODE, F::CW, F::RPW, F::NW, F::G, DETECT>), dim3(grid),
                        dim3(64 * F::NW), 0, st, a);
 }
 
-template <typename T, int OP, int MODE, int FAM>
+template <typename T, int OP, int MODE, int FAM, bool DETECT = false>
 static PersistentFns persistent_fns_t() {
     using F = Family<T, FAM>;
     PersistentFns f;
-    f.kernel = (const void *)&persistent_chain_kernel<T, OP, MODE, F::CW, F::RPW, F::NW, F::G>;
-    f.launch = &launch_persistent<T, OP, MODE, FAM>;
+    f.kernel = (const void *)&persistent_chain_kernel<T, OP, MODE, F::CW, F::RPW, F::NW, F::G, DETECT>;
+    f.launch = &launch_persistent<T, OP, MODE, FAM, DETECT>;
     f.threads = 64 * F::NW;
     return f;
 }
@@ -1122,6 +1122,14 @@ static PersistentFns persistent_fns_m(int fam) {
     }
 }
 
+// Plans with run-to-stability items: change bits on, geodesic, 128 x 128
+// regions of 16 waves (the built-in family).
+template <typename T>
+static PersistentFns persistent_fns_detect(int op) {
+    return op == OP_DILATE ? persistent_fns_t<T, OP_DILATE, MODE_GEODESIC, FAM_128W, true>()
+                           : persistent_fns_t<T, OP_ERODE, MODE_GEODESIC, FAM_128W, true>();
+}
+
 template <typename T>
 static PersistentFns persistent_fns_d(int op, int mode, int fam) {
     if (op == OP_DILATE)
@@ -1131,7 +1139,15 @@ static PersistentFns persistent_fns_d(int op, int mode, int fam) {
                                  : persistent_fns_m<T, OP_ERODE, MODE_PLAIN>(fam);
 }
 
-static PersistentFns persistent_fns(gc_dtype d, int op, int mode, int fam) {
+static PersistentFns persistent_fns(gc_dtype d, int op, int mode, int fam, bool detect) {
+    if (detect) {
+        switch (d) {
+            case GC_U8: return persistent_fns_detect<uint8_t>(op);
+            case GC_F32: return persistent_fns_detect<float>(op);
+            case GC_F64: return persistent_fns_detect<double>(op);
+        }
+        return PersistentFns{};
+    }
     switch (d) {
         case GC_U8: return persistent_fns_d<uint8_t>(op, mode, fam);
         case GC_F32: return persistent_fns_d<float>(op, mode, fam);
@@ -1145,6 +1161,10 @@ static PersistentFns persistent_fns(gc_dtype d, int op, int mode, int fam) {
 static int persistent_kmax(int fam) { return region_side(fam) / 3; }
 // Built-in steps per block for batches: with many items in flight the
 // per-item latency is hidden, so a shallower block (less halo) wins.
+// Run-to-stability items in plans: steps per block and blocks per replay.
+constexpr int STAB_K = 20;
+constexpr int STAB_BLOCKS = 8;
+
 static int default_persistent_k(int fam) {
     const int side = region_side(fam);
     return side == 128 ? 20 : side == 96 ? 16 : 12;
@@ -1196,6 +1216,13 @@ struct gc_plan {
     hipGraphExec_t exec = nullptr;
     hipStream_t last_stream = nullptr;
     bool launched = false;
+    // run-to-stability items (n_steps < 0): rounds of STAB_BLOCKS blocks of
+    // STAB_K steps, the host deciding between graph replays
+    std::vector<geochain::PlanImage> imgs_init;  // the image table as recorded
+    std::vector<int> img_item;                   // plan image -> gc_item index
+    std::vector<int> stab_imgs;                  // plan images that run to stability
+    uint32_t *change_h = nullptr;                // pinned copy of their change words
+    std::vector<int64_t> steps;                  // per gc_item, of the last launch
 };
 
 namespace geochain {
@@ -1210,6 +1237,7 @@ static void plan_free(gc_plan *p) {
     if (p->words_d) (void)hipFree(p->words_d);
     if (p->ws) (void)hipFree(p->ws);
     if (p->error_h) (void)hipHostFree(p->error_h);
+    if (p->change_h) (void)hipHostFree(p->change_h);
     delete p;
 }
 
@@ -1286,7 +1314,8 @@ static int plan_build(gc_dtype dtype, int op, const gc_item *items, int32_t n_it
         const gc_item &it = items[i];
         int rc = validate_images(dtype, it.marker, it.mask, it.out, it.shape);
         if (rc != GC_OK) return fail(rc, "item %d: %s", i, g_last_error.c_str());
-        if (it.n_steps < 0) return fail(GC_ERR_UNSUPPORTED, "item %d: n_steps < 0", i);
+        if (it.n_steps < 0 && !it.mask)
+            return fail(GC_ERR_UNSUPPORTED, "item %d: only geodesic items run to stability (n_steps < 0)", i);
         if (it.n_steps > INT32_MAX / 2) return fail(GC_ERR_UNSUPPORTED, "item %d: n_steps too large", i);
         const bool empty = it.shape.width == 0 || it.shape.height == 0;
         if (empty) continue;
@@ -1309,7 +1338,19 @@ static int plan_build(gc_dtype dtype, int op, const gc_item *items, int32_t n_it
         return fail(GC_ERR_HIP, "hipGetDevice failed");
     }
 
-    const PlanChoice choice = forced ? *forced : choose_plan_batch(dtype, op, mode, p->items);
+    bool stab = false;
+    for (const auto &it : p->items) stab = stab || (it.n_steps < 0 && it.shape.width > 0 && it.shape.height > 0);
+    PlanChoice choice = forced ? *forced : choose_plan_batch(dtype, op, mode, p->items);
+    if (stab) {
+        // Run-to-stability plans keep the built-in launch shape: 128 x 128
+        // regions, STAB_K steps per block (the change bits of a block are one
+        // 32-bit word).
+        choice.fam = FAM_128W;
+        for (size_t i = 0; i < p->items.size(); ++i) {
+            const int64_t ni = p->items[i].n_steps;
+            choice.k[i] = ni > 0 && ni < STAB_K ? (int)ni : STAB_K;
+        }
+    }
     p->fam = choice.fam;
     const int side = region_side(p->fam);
 
@@ -1331,13 +1372,16 @@ static int plan_build(gc_dtype dtype, int op, const gc_item *items, int32_t n_it
         im.pitch = it.shape.pitch;
         im.width = (int32_t)it.shape.width;
         im.height = (int32_t)it.shape.height;
-        im.n_steps = (int32_t)it.n_steps;
         im.k = choice.k[i];
+        // a run-to-stability image runs STAB_BLOCKS blocks per replay
+        im.n_steps = it.n_steps < 0 ? STAB_BLOCKS * im.k : (int32_t)it.n_steps;
         im.core_x = side - 2 * im.k;
         im.core_y = side - 2 * im.k;
         im.tiles_x = (int32_t)((it.shape.width + im.core_x - 1) / im.core_x);
         im.tiles_y = (int32_t)((it.shape.height + im.core_y - 1) / im.core_y);
-        im.blocks = (int32_t)((it.n_steps + im.k - 1) / im.k);
+        im.blocks = (int32_t)((im.n_steps + im.k - 1) / im.k);
+        im.active = 1;
+        if (it.n_steps < 0) p->stab_imgs.push_back((int)imgs.size());
         im.flag_base = (int32_t)std::min<int64_t>(flags, INT32_MAX);
         flags += (int64_t)im.tiles_x * im.tiles_y;
         im.src0_ws1 = (it.out == it.marker && im.blocks == 1) ? 1 : 0;
@@ -1348,7 +1392,7 @@ static int plan_build(gc_dtype dtype, int op, const gc_item *items, int32_t n_it
         ws_bytes += 2 * aligned;
         imgs.push_back(im);
         img_of_item.push_back(i);
-        p->px_steps += it.shape.width * it.shape.height * it.n_steps;
+        if (it.n_steps > 0) p->px_steps += it.shape.width * it.shape.height * it.n_steps;
         p->max_k = std::max(p->max_k, im.k);
     }
     // items ordered by block, longest chains first within a block
@@ -1378,6 +1422,19 @@ static int plan_build(gc_dtype dtype, int op, const gc_item *items, int32_t n_it
 
     // ---- device allocations ----
     auto bail = [&](int rc) { plan_free(p); return rc; };
+    // counters: [0] spare, [1] error word, then one per tile, then STAB_BLOCKS
+    // change words per run-to-stability image
+    const int64_t n_change = (int64_t)p->stab_imgs.size() * STAB_BLOCKS;
+    p->n_words = 2 + flags + n_change;
+    if (hipMalloc((void **)&p->words_d, p->n_words * 4) != hipSuccess ||
+        hipHostMalloc((void **)&p->error_h, 4, hipHostMallocDefault) != hipSuccess ||
+        (n_change > 0 && hipHostMalloc((void **)&p->change_h, n_change * 4, hipHostMallocDefault) != hipSuccess)) {
+        (void)hipGetLastError();
+        return bail(fail(GC_ERR_NO_MEMORY, "plan counters"));
+    }
+    *p->error_h = 0;
+    for (size_t q = 0; q < p->stab_imgs.size(); ++q)
+        imgs[p->stab_imgs[q]].change = p->words_d + 2 + flags + (int64_t)q * STAB_BLOCKS;
     if (!imgs.empty()) {
         if (hipMalloc(&p->ws, ws_bytes) != hipSuccess) { (void)hipGetLastError(); return bail(fail(GC_ERR_NO_MEMORY, "plan workspace of %zu bytes", ws_bytes)); }
         for (size_t j = 0; j < imgs.size(); ++j) {
@@ -1396,16 +1453,12 @@ static int plan_build(gc_dtype dtype, int op, const gc_item *items, int32_t n_it
             hipMemcpy(p->items_d, plan_items.data(), plan_items.size() * sizeof(PlanItem), hipMemcpyHostToDevice) != hipSuccess)
             return bail(fail(GC_ERR_HIP, "uploading plan tables"));
     }
-    p->n_words = 2 + (int64_t)flags;
-    if (hipMalloc((void **)&p->words_d, p->n_words * 4) != hipSuccess ||
-        hipHostMalloc((void **)&p->error_h, 4, hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
-        return bail(fail(GC_ERR_NO_MEMORY, "plan counters"));
-    }
-    *p->error_h = 0;
+    p->imgs_init = imgs;
+    p->img_item = img_of_item;
+    p->steps.assign(p->items.size(), -1);
 
     // ---- grid: as many workgroups as fit on the device at once ----
-    const PersistentFns fns = persistent_fns(dtype, op, mode, p->fam);
+    const PersistentFns fns = persistent_fns(dtype, op, mode, p->fam, n_change > 0);
     int per_cu = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fns.kernel, fns.threads, 0) != hipSuccess)
         return bail(fail(GC_ERR_HIP, "occupancy query failed"));
@@ -1449,6 +1502,9 @@ static int plan_build(gc_dtype dtype, int op, const gc_item *items, int32_t n_it
         cap_ok = cap_ok && hipGetLastError() == hipSuccess;
         // Error word to pinned host memory for gc_plan_status.
         cap_ok = cap_ok && hipMemcpyAsync(p->error_h, p->words_d + 1, 4, hipMemcpyDeviceToHost, p->cap_stream) == hipSuccess;
+        if (n_change > 0)
+            cap_ok = cap_ok && hipMemcpyAsync(p->change_h, p->words_d + 2 + flags, n_change * 4, hipMemcpyDeviceToHost,
+                                              p->cap_stream) == hipSuccess;
     }
     hipError_t ec = hipStreamEndCapture(p->cap_stream, &p->graph);
     if (ec != hipSuccess || !cap_ok) return bail(fail(GC_ERR_HIP, "graph capture failed: %s", hipGetErrorString(ec)));
@@ -1952,6 +2008,8 @@ int gc_plan_tune(gc_plan *plan, double *best_ms) {
     int dev = 0;
     GC_HIP(hipGetDevice(&dev));
     if (dev != plan->device) return fail(GC_ERR_INVALID_ARG, "plan belongs to device %d", plan->device);
+    if (!plan->stab_imgs.empty())
+        return fail(GC_ERR_UNSUPPORTED, "plans with run-to-stability items keep the built-in launch shape");
     if (plan->launched) GC_HIP(hipStreamSynchronize(plan->last_stream));
     const size_t es = elem_size(plan->dtype);
     const size_t n = plan->items.size();
@@ -2025,11 +2083,79 @@ int gc_plan_launch(gc_plan *plan, void *hip_stream) {
     int dev = 0;
     GC_HIP(hipGetDevice(&dev));
     if (dev != plan->device) return fail(GC_ERR_INVALID_ARG, "plan belongs to device %d", plan->device);
-    const int pr = prof_begin((hipStream_t)hip_stream, 0);
-    GC_HIP(hipGraphLaunch(plan->exec, (hipStream_t)hip_stream));
-    prof_end(pr, (hipStream_t)hip_stream);
-    plan->last_stream = (hipStream_t)hip_stream;
+    hipStream_t st = (hipStream_t)hip_stream;
+    for (size_t i = 0; i < plan->items.size(); ++i) {
+        const gc_item &it = plan->items[i];
+        const bool empty = it.shape.width == 0 || it.shape.height == 0;
+        plan->steps[i] = it.n_steps >= 0 ? it.n_steps : (empty ? 0 : -1);
+    }
+    if (plan->stab_imgs.empty()) {
+        const int pr = prof_begin(st, 0);
+        GC_HIP(hipGraphLaunch(plan->exec, st));
+        prof_end(pr, st);
+        plan->last_stream = st;
+        plan->launched = true;
+        return GC_OK;
+    }
+    // Run-to-stability items: each replay runs STAB_BLOCKS blocks of STAB_K
+    // steps of every active image and records, per block, the OR over its
+    // tiles of the per-step change bits.  Once a full step changes nothing the
+    // state is a fixed point, so the bits of an image form a run of ones: the
+    // first zero is its step count, and the state after the replay is the
+    // result.  Images that changed at every step continue from their output
+    // in the next replay; converged and fixed-length images sit it out.
+    plan->last_stream = st;
     plan->launched = true;
+    std::vector<geochain::PlanImage> tab = plan->imgs_init;
+    const size_t tab_bytes = tab.size() * sizeof(geochain::PlanImage);
+    GC_HIP(hipMemcpyAsync(plan->images_d, tab.data(), tab_bytes, hipMemcpyHostToDevice, st));
+    const size_t n_stab = plan->stab_imgs.size();
+    std::vector<int64_t> changed(n_stab, 0);
+    std::vector<char> done(n_stab, 0);
+    size_t left = n_stab;
+    while (left > 0) {
+        GC_HIP(hipGraphLaunch(plan->exec, st));
+        GC_HIP(hipStreamSynchronize(st));
+        if (*plan->error_h) return fail(GC_ERR_HIP, "a dependency wait inside the batch kernel hit its bound");
+        for (auto &im : tab) im.active = 0;  // fixed-length images are complete after the first replay
+        for (size_t q = 0; q < n_stab; ++q) {
+            if (done[q]) continue;
+            const int j = plan->stab_imgs[q];
+            const uint32_t *w = plan->change_h + q * STAB_BLOCKS;
+            const uint32_t full = (1u << tab[j].k) - 1u;
+            bool stable = false;
+            for (int b = 0; b < STAB_BLOCKS && !stable; ++b) {
+                if (w[b] == full) {
+                    changed[q] += tab[j].k;
+                } else {
+                    changed[q] += __builtin_ctz(~w[b]);
+                    stable = true;
+                }
+            }
+            const gc_item &it = plan->items[plan->img_item[j]];
+            if (stable) {
+                done[q] = 1;
+                --left;
+                plan->steps[plan->img_item[j]] = changed[q];
+            } else if (changed[q] > it.shape.width * it.shape.height + 1) {
+                // a reconstruction changes something at each step along a path
+                // of distinct pixels, so this bound is never reached
+                return fail(GC_ERR_NOT_CONVERGED, "item %d did not converge in %lld steps", plan->img_item[j],
+                            (long long)changed[q]);
+            } else {
+                tab[j].active = 1;
+                tab[j].marker = tab[j].out;  // continue from this replay's result
+            }
+        }
+        if (left > 0) GC_HIP(hipMemcpyAsync(plan->images_d, tab.data(), tab_bytes, hipMemcpyHostToDevice, st));
+    }
+    return GC_OK;
+}
+
+int gc_plan_steps(const gc_plan *plan, int64_t *steps) {
+    g_last_error.clear();
+    if (!plan || !steps) return fail(GC_ERR_INVALID_ARG, "plan or steps is NULL");
+    for (size_t i = 0; i < plan->steps.size(); ++i) steps[i] = plan->steps[i];
     return GC_OK;
 }
 

@@ -22,7 +22,15 @@
 // ws[b&1], except the last block which writes out.  A tile's block b may
 // overwrite ws[b&1] only after its neighbours finished block b-1, which was
 // the last reader of that buffer, so the same counters also order the
-// write-after-read reuse of the two work buffers.
+// write-after-read reuse of the two work buffers.  With two or more blocks
+// the marker may be out itself (in place, or a run-to-stability image that
+// continues from its previous result): the last block writes a tile's core
+// only after its neighbours, the only other readers of it, passed block 0.
+//
+// DETECT (plans with run-to-stability images): each block ORs the per-step
+// change bits of its core into the image's word for that block, so the host
+// can tell after the launch whether, and at which step, the image stopped
+// changing.  Images whose `active` flag is 0 are skipped whole.
 #pragma once
 
 #include "chain_block.hpp"
@@ -44,7 +52,9 @@ struct PlanImage {
     int32_t blocks;
     int32_t flag_base;  // first per-tile counter of this image
     int32_t src0_ws1;   // block 0 reads ws1 (in-place single-block chains)
-    int32_t pad;
+    int32_t active;     // 0: the image's items are skipped in this launch
+    uint32_t *change;   // run-to-stability images: per block, the OR over
+                        // tiles of the block's per-step change bits (else null)
 };
 
 struct PlanItem {
@@ -85,7 +95,7 @@ __device__ __forceinline__ bool wait_neighbours(const PersistentArgs &a, const P
     return done;
 }
 
-template <typename T, int OP, int MODE, int CW, int RPW, int NW, int G = 1>
+template <typename T, int OP, int MODE, int CW, int RPW, int NW, int G = 1, bool DETECT = false>
 __global__ __launch_bounds__(64 * NW) void persistent_chain_kernel(PersistentArgs a) {
     using R = typename RegOf<T>::type;
     __shared__ __attribute__((aligned(16))) R xch[2][NW][2 * G][lanes_per_group<G>() * CW];
@@ -102,6 +112,9 @@ __global__ __launch_bounds__(64 * NW) void persistent_chain_kernel(PersistentArg
     for (int it = first; it < a.n_items; it += gridDim.x) {
         const PlanItem item = a.items[it];
         const PlanImage &im = a.images[item.image];
+        // the same item for every wave: a uniform skip, barriers stay matched;
+        // only items of the same image depend on a skipped item
+        if (!im.active) continue;
         const int tx = item.tile % im.tiles_x;
         const int ty = item.tile / im.tiles_x;
         const int b = item.block;
@@ -144,7 +157,10 @@ __global__ __launch_bounds__(64 * NW) void persistent_chain_kernel(PersistentArg
         // that every XCD sees by themselves, so the agent-scope release below
         // has (almost) no dirty L2 lines to write back.  The release is still
         // what orders them before the counter.
-        chain_block_dispatch<T, OP, MODE, false, CW, RPW, NW, G, true>(ba, rx0, ry0, xch);
+        const uint32_t bits = chain_block_dispatch<T, OP, MODE, DETECT, CW, RPW, NW, G, true>(ba, rx0, ry0, xch);
+        if constexpr (DETECT) {
+            if (bits != 0 && im.change != nullptr && (tid & 63) == 0) atomicOr(im.change + b, bits);
+        }
 
         // ---- publish: stores first, then the tile's counter ----
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");

@@ -249,8 +249,10 @@ class BatchPlan:
 
     items: sequence of (marker, mask_or_None, n_steps) or (marker, mask,
     n_steps, out).  All images share one dtype and device; all items are
-    geodesic (mask given) or all plain.  The outputs are allocated here when
-    not given.  launch() replays the recorded graph on the current stream.
+    geodesic (mask given) or all plain.  n_steps < 0 (geodesic items) runs
+    to stability; steps() then gives each item's step count, and launch()
+    waits for the result.  The outputs are allocated here when not given.
+    launch() replays the recorded graph on the current stream.
     """
 
     def __init__(self, op, items):
@@ -298,6 +300,13 @@ class BatchPlan:
 
     def status(self):
         abi.check(abi.gc_plan_status(self._plan), "gc_plan_status")
+
+    def steps(self):
+        """Steps of the last launch per item: n_steps for fixed-length items,
+        the steps that changed a pixel for run-to-stability items (n < 0)."""
+        arr = (ctypes.c_int64 * max(len(self.outs), 1))()
+        abi.check(abi.gc_plan_steps(self._plan, arr), "gc_plan_steps")
+        return [int(arr[i]) for i in range(len(self.outs))]
 
     def info(self):
         px, items = ctypes.c_int64(), ctypes.c_int64()

@@ -85,6 +85,11 @@ def test_size_limits():
         assert "not supported" in abi.last_error()
 
 
+def test_plan_steps_validates():
+    steps = (ctypes.c_int64 * 1)()
+    assert abi.gc_plan_steps(None, steps) == abi.GC_ERR_INVALID_ARG
+
+
 def test_aliasing_is_rejected():
     s = shape(100, 100, 128)
     # out == mask

@@ -229,3 +229,98 @@ def test_plan_with_image_beyond_one_launch_grid():
         plan.close()
     del F, M, plan
     torch.cuda.empty_cache()
+
+
+def _serpentine(h, w):
+    """Mask open along every even row, the rows joined alternately at the
+    right and the left end; marker: one seed at the corridor's start."""
+    m = np.zeros((h, w), np.uint8)
+    m[0::2, :] = 255
+    for y in range(1, h, 2):
+        m[y, w - 1 if (y // 2) % 2 == 0 else 0] = 255
+    f = np.zeros_like(m)
+    f[0, 0] = 255
+    return f, m
+
+
+def _stability_items(dtype, rng):
+    """(marker, mask, n_steps, in_place) host items for a mixed plan."""
+    items = []
+    for shape in ((200, 300), (97, 131)):
+        f, m = rand_img(shape, dtype, rng), rand_img(shape, dtype, rng)
+        items.append((np.minimum(f, m), m, -1, False))
+    f, m = rand_img((120, 77), dtype, rng), rand_img((120, 77), dtype, rng)
+    items.append((np.minimum(f, m), m, -1, True))          # in place
+    seed_m = np.full((150, 260), 5, dtype)
+    seed_f = np.zeros_like(seed_m)
+    seed_f[0, 0] = 5                                         # 259 steps: two replays
+    items.append((seed_f, seed_m, -1, False))
+    f, m = _serpentine(31, 64)
+    items.append((f.astype(dtype), m.astype(dtype), -1, False))   # about a thousand steps
+    f, m = rand_img((64, 90), dtype, rng), rand_img((64, 90), dtype, rng)
+    items.append((f, m, 37, False))                          # fixed length
+    items.append((f, m, 0, False))
+    return items
+
+
+@pytest.mark.parametrize("op", ["dilate", "erode"])
+@pytest.mark.parametrize("dtype", [np.uint8, np.float32])
+def test_plan_items_run_to_stability(op, dtype):
+    """Run-to-stability items (n_steps < 0) beside fixed-length ones in one
+    plan: every image and every step count equals the oracle's (the
+    reconstruction for n < 0, the chain otherwise), across replays that
+    retire converged images and continue the others (the corridor needs
+    about a thousand steps, several replays of 160)."""
+    rng = np.random.default_rng(61)
+    host_items = _stability_items(dtype, rng)
+    if op == "erode":   # reconstruction by erosion: marker above the mask
+        host_items = [(np.maximum(f, m) if n < 0 else f, m, n, ip) for f, m, n, ip in host_items]
+        host_items[3] = (np.full((150, 260), 5, dtype), np.zeros((150, 260), dtype), -1, False)
+        host_items[3][0][0, 0] = 0
+        sf, sm = _serpentine(31, 64)
+        host_items[4] = ((255 - sf).astype(dtype), (255 - sm).astype(dtype), -1, False)
+    code = oracle.DILATE if op == "dilate" else oracle.ERODE
+    dev_items = []
+    for f, m, n, ip in host_items:
+        F, M = dev(f), dev(m)
+        dev_items.append((F, M, n, F) if ip else (F, M, n))
+    plan = gc.BatchPlan(op, dev_items)
+    try:
+        plan.launch()
+        plan.status()
+        steps = plan.steps()
+        for i, ((f, m, n, ip), o) in enumerate(zip(host_items, plan.outs)):
+            if n < 0:
+                ref, ref_steps, conv = oracle.reconstruct(code, f, m)
+                assert conv and steps[i] == ref_steps, (i, steps[i], ref_steps)
+            else:
+                ref = oracle.chain(code, f, n, m)
+                assert steps[i] == n
+            assert np.array_equal(host(o), ref), f"item {i}: {f.shape} n={n} in_place={ip}"
+        assert max(steps) > 160       # at least one image needed several replays
+    finally:
+        plan.close()
+
+
+def test_plan_relaunch_and_refusals():
+    """A run-to-stability plan launched twice gives the same result (each
+    launch starts from the markers); plain items cannot run to stability;
+    such plans keep the built-in launch shape."""
+    rng = np.random.default_rng(71)
+    f, m = rand_img((140, 210), np.uint8, rng), rand_img((140, 210), np.uint8, rng)
+    F, M = dev(np.minimum(f, m)), dev(m)
+    plan = gc.BatchPlan("dilate", [(F, M, -1)])
+    try:
+        plan.launch()
+        first = plan.outs[0].clone()
+        s1 = plan.steps()
+        plan.launch()
+        assert torch.equal(plan.outs[0], first) and plan.steps() == s1
+        ref, ref_steps, _ = oracle.reconstruct(oracle.DILATE, np.minimum(f, m), m)
+        assert np.array_equal(host(first), ref) and s1 == [ref_steps]
+        with pytest.raises(gc.GeochainError):
+            plan.tune()
+    finally:
+        plan.close()
+    with pytest.raises(gc.GeochainError):
+        gc.BatchPlan("dilate", [(F, None, -1)])
