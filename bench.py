@@ -160,11 +160,12 @@ def cpu_baseline(f, m, n_steps, repeats=3):
     }
 
 
-def verify(S, N, F, M, f, m, headline_ref, dev, with_extra=True, batch_outs=None):
+def verify(S, N, F, M, f, m, headline_ref, dev, with_extra=True, batch_outs=None, rec_batch_outs=None):
     """Bitwise parity with the oracle of what the run measured: each GPU
     result is computed once more, untimed, and compared element by element
     (and by step count where there is one).  The headline's oracle result is
-    the CPU baseline's own.  Of the batch every 16th image is checked; the
+    the CPU baseline's own.  Of the batch every 16th image is checked, of the
+    batched reconstruction every 4th (image and step count); the
     gradient's parity is left to the test suite (its oracle takes minutes
     at this size).  The batch's images are those of the timed plan's last
     replay."""
@@ -225,6 +226,13 @@ def verify(S, N, F, M, f, m, headline_ref, dev, with_extra=True, batch_outs=None
         ok["batched_64_uneven_u8_every_16th"] = all(
             bool(np.array_equal(o, oracle.chain(oracle.DILATE, items[i].marker, items[i].n_steps, items[i].mask)))
             for i, o in batch_outs.items())
+    if rec_batch_outs:
+        items = workloads.batch_u8().items
+        good = True
+        for i, (o, st_) in rec_batch_outs.items():
+            r, rs, _ = oracle.reconstruct(oracle.DILATE, items[i].marker, items[i].mask)
+            good = good and bool(np.array_equal(o, r)) and st_ == rs
+        ok["batched_reconstruction_16_u8_every_4th"] = good
     return ok
 
 
@@ -325,6 +333,7 @@ def main():
 
     extra = {}
     batch_outs = None
+    rec_batch_outs = None
     if not args.no_extra:
         fe, me = workloads.headline_u8_erosion(size=S)
         Fe, Me = torch.from_numpy(fe).to(dev), torch.from_numpy(me).to(dev)
@@ -415,6 +424,31 @@ def main():
         batch_outs = {i: plan.outs[i].cpu().numpy() for i in range(0, len(items), 16)}
         plan.close()
         del items
+        # Batched reconstruction: the first 16 images of that batch run to
+        # stability in one plan (replays of 8 blocks of 20 steps, retired on
+        # the host once they stop changing), beside the same reconstructions
+        # as 16 single-image calls.
+        rec_items = [(torch.from_numpy(it.marker).to(dev), torch.from_numpy(it.mask).to(dev), -1)
+                     for it in batch.items[:16]]
+        rplan = gc.BatchPlan("dilate", rec_items)
+        ms_rb = timed(rplan.launch, max(3, args.steps // 4), 1)
+        rsteps = rplan.steps()
+        rec_outs = [torch.empty_like(mk) for _, mk, _ in rec_items]
+
+        def single_reconstructions():
+            for (mk, msk, _), o in zip(rec_items, rec_outs):
+                gc.reconstruct_by_dilation(mk, msk, out=o)
+
+        ms_rs = timed(single_reconstructions, max(3, args.steps // 4), 1)
+        px_rb = sum(mk.numel() * st_ for (mk, _, _), st_ in zip(rec_items, rsteps))
+        extra["batched_reconstruction_16_u8"] = {
+            "ms": round(ms_rb, 3), "single_image_calls_ms": round(ms_rs, 3),
+            "vs_single_image_calls": round(ms_rs / ms_rb, 3),
+            "gpx_steps_per_s": round(px_rb / ms_rb / 1e6, 2), "steps_min_max": [min(rsteps), max(rsteps)]}
+        torch.cuda.synchronize()
+        rec_batch_outs = {i: (rplan.outs[i].cpu().numpy(), rsteps[i]) for i in range(0, len(rec_items), 4)}
+        rplan.close()
+        del rec_items, rec_outs
         # Differentiable: 16 x 1024^2 f32, 200 steps, forward + backward.
         fd, md, gd = workloads.differentiable_f32(size=S)
         Fd, Md, Gd = (torch.from_numpy(a).to(dev) for a in (fd, md, gd))
@@ -500,7 +534,7 @@ def main():
         headline_ref, line["cpu_baseline"] = cpu_baseline(f, m, N)
         extra["cpu_oracle_1_thread"] = cpu_single_thread(f, m, 150)
         line["parity"] = verify(S, N, F, M, f, m, headline_ref, dev, with_extra=not args.no_extra,
-                                batch_outs=batch_outs)
+                                batch_outs=batch_outs, rec_batch_outs=rec_batch_outs)
     # Context, not a baseline: the paper claims real time (30 FPS) for chains
     # of 1500 filters on 1024^2 images, i.e. at least 47.2 Gpx-steps/s on its
     # test CPUs; it reports no time for this exact workload.
