@@ -425,7 +425,7 @@ def main():
         plan.close()
         del items
         # Batched reconstruction: the first 16 images of that batch run to
-        # stability in one plan (replays of 8 blocks of 20 steps, retired on
+        # stability in one plan (replays of 4 blocks of 20 steps, retired on
         # the host once they stop changing), beside the same reconstructions
         # as 16 single-image calls.
         rec_items = [(torch.from_numpy(it.marker).to(dev), torch.from_numpy(it.mask).to(dev), -1)

@@ -251,7 +251,7 @@ int gc_quasi_distance(gc_dtype dtype, const void *f, int32_t *dist, void *residu
  * gc_plan_launch replays the graph on hip_stream (asynchronous).  Launches
  * of one plan must not overlap each other (they share the workspace).
  * With run-to-stability items it is synchronous instead: each replay runs
- * every active image for 8 blocks of 20 steps while the kernel records, per
+ * every active image for 4 blocks of 20 steps while the kernel records, per
  * block, which steps changed a pixel; between replays the host retires the
  * images that reached a step without change (their result is then a fixed
  * point) and the others continue from their output.  Fixed-length items

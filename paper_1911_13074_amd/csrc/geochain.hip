@@ -1163,7 +1163,7 @@ static int persistent_kmax(int fam) { return region_side(fam) / 3; }
 // per-item latency is hidden, so a shallower block (less halo) wins.
 // Run-to-stability items in plans: steps per block and blocks per replay.
 constexpr int STAB_K = 20;
-constexpr int STAB_BLOCKS = 8;
+constexpr int STAB_BLOCKS = 4;
 
 static int default_persistent_k(int fam) {
     const int side = region_side(fam);

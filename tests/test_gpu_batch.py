@@ -270,7 +270,7 @@ def test_plan_items_run_to_stability(op, dtype):
     plan: every image and every step count equals the oracle's (the
     reconstruction for n < 0, the chain otherwise), across replays that
     retire converged images and continue the others (the corridor needs
-    about a thousand steps, several replays of 160)."""
+    about a thousand steps, several replays of 80)."""
     rng = np.random.default_rng(61)
     host_items = _stability_items(dtype, rng)
     if op == "erode":   # reconstruction by erosion: marker above the mask
