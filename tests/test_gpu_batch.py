@@ -264,13 +264,13 @@ def _stability_items(dtype, rng):
 
 
 @pytest.mark.parametrize("op", ["dilate", "erode"])
-@pytest.mark.parametrize("dtype", [np.uint8, np.float32])
+@pytest.mark.parametrize("dtype", DTYPES)
 def test_plan_items_run_to_stability(op, dtype):
     """Run-to-stability items (n_steps < 0) beside fixed-length ones in one
-    plan: every image and every step count equals the oracle's (the
-    reconstruction for n < 0, the chain otherwise), across replays that
-    retire converged images and continue the others (the corridor needs
-    about a thousand steps, several replays of 80)."""
+    plan, u8, f32 and f64: every image and every step count equals the
+    oracle's (the reconstruction for n < 0, the chain otherwise), across
+    replays that retire converged images and continue the others (the
+    corridor needs about a thousand steps, several replays of 80)."""
     rng = np.random.default_rng(61)
     host_items = _stability_items(dtype, rng)
     if op == "erode":   # reconstruction by erosion: marker above the mask
