@@ -311,6 +311,7 @@ def test_plan_relaunch_and_refusals():
     F, M = dev(np.minimum(f, m)), dev(m)
     plan = gc.BatchPlan("dilate", [(F, M, -1)])
     try:
+        assert plan.steps() == [-1]      # not launched yet
         plan.launch()
         first = plan.outs[0].clone()
         s1 = plan.steps()
