@@ -825,44 +825,103 @@ __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int 
 #pragma unroll
         for (int j = 0; j < H; ++j) row_pass(j);
         publish(0);
-        for (int s = 0; s < busy; ++s) {
-            uint32_t nv[H][CW];
-            uint32_t changed = 0;
+        if constexpr (!D) {
+            for (int s = 0; s < busy; ++s) {
+                uint32_t nv[H][CW];
+                uint32_t changed = 0;
 #pragma unroll
-            for (int c = 0; c < CW; ++c) {
+                for (int c = 0; c < CW; ++c) {
 #pragma unroll
-                for (int j = 1; j < H - 1; ++j) finish(j, c, P::pick3(h[j - 1][c], h[j][c], h[j + 1][c]), nv, changed);
-            }
-            // keep the seams, which wait for the exchange reads, after the
-            // middle registers, which cover the reads' latency
-            __builtin_amdgcn_sched_barrier(0);
+                    for (int j = 1; j < H - 1; ++j) finish(j, c, P::pick3(h[j - 1][c], h[j][c], h[j + 1][c]), nv, changed);
+                }
+                // keep the seams, which wait for the exchange reads, after the
+                // middle registers, which cover the reads' latency
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int c = 0; c < CW; ++c) {
-                // seams: rows above register 0 are (wave above's last row,
-                // this wave's row H - 1); rows below register H - 1 are
-                // (this wave's row H, wave below's first row)
-                const uint32_t up0 = __builtin_amdgcn_alignbit(h[H - 1][c], above[c], 16);
-                const uint32_t dnl = __builtin_amdgcn_alignbit(below[c], h[0][c], 16);
-                if constexpr (H == 1) {
-                    finish(0, c, P::pick3(up0, h[0][c], dnl), nv, changed);
-                } else {
-                    finish(0, c, P::pick3(up0, h[0][c], h[1][c]), nv, changed);
-                    finish(H - 1, c, P::pick3(h[H - 2][c], h[H - 1][c], dnl), nv, changed);
+                for (int c = 0; c < CW; ++c) {
+                    // seams: rows above register 0 are (wave above's last row,
+                    // this wave's row H - 1); rows below register H - 1 are
+                    // (this wave's row H, wave below's first row)
+                    const uint32_t up0 = __builtin_amdgcn_alignbit(h[H - 1][c], above[c], 16);
+                    const uint32_t dnl = __builtin_amdgcn_alignbit(below[c], h[0][c], 16);
+                    if constexpr (H == 1) {
+                        finish(0, c, P::pick3(up0, h[0][c], dnl), nv, changed);
+                    } else {
+                        finish(0, c, P::pick3(up0, h[0][c], h[1][c]), nv, changed);
+                        finish(H - 1, c, P::pick3(h[H - 2][c], h[H - 1][c], dnl), nv, changed);
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < H; ++j)
+#pragma unroll
+                    for (int c = 0; c < CW; ++c) v[j][c] = nv[j][c];
+                if constexpr (D) {
+                    if (__builtin_amdgcn_ballot_w64(changed != 0)) step_bits |= 1u << s;
+                }
+                if (s + 1 < busy) {
+                    row_pass(0);
+                    if constexpr (H > 1) row_pass(H - 1);
+                    publish((s + 1) & 1);
+#pragma unroll
+                    for (int j = 1; j < H - 1; ++j) row_pass(j);
                 }
             }
+        } else {
+            // With change detection each step reads the previous state after
+            // the new one exists, so a loop that copies new into old would
+            // move every register each step; two steps per iteration with the
+            // roles of v and v2 swapped keep both in place.
+            uint32_t v2[H][CW];
+            auto row_pass_of = [&](uint32_t (&st)[H][CW], int j) {
+                const uint32_t left = lane_shift<DPP_WAVE_SHR1>(st[j][1]);
+                const uint32_t right = lane_shift<DPP_WAVE_SHL1>(st[j][0]);
+                h[j][0] = P::pick3(left, st[j][0], st[j][1]);
+                h[j][1] = P::pick3(st[j][0], st[j][1], right);
+            };
+            auto step = [&](int s, uint32_t (&cur)[H][CW], uint32_t (&nxt)[H][CW]) {
+                uint32_t changed = 0;
+                auto fin = [&](int j, int c, uint32_t x) {
+                    if constexpr (CLAMP) x = P::clamp(x, m[j][c]);
+                    changed |= (x ^ cur[j][c]) & cmask[j][c];
+                    nxt[j][c] = x;
+                };
 #pragma unroll
-            for (int j = 0; j < H; ++j)
+                for (int c = 0; c < CW; ++c) {
 #pragma unroll
-                for (int c = 0; c < CW; ++c) v[j][c] = nv[j][c];
-            if constexpr (D) {
+                    for (int j = 1; j < H - 1; ++j) fin(j, c, P::pick3(h[j - 1][c], h[j][c], h[j + 1][c]));
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int c = 0; c < CW; ++c) {
+                    const uint32_t up0 = __builtin_amdgcn_alignbit(h[H - 1][c], above[c], 16);
+                    const uint32_t dnl = __builtin_amdgcn_alignbit(below[c], h[0][c], 16);
+                    if constexpr (H == 1) {
+                        fin(0, c, P::pick3(up0, h[0][c], dnl));
+                    } else {
+                        fin(0, c, P::pick3(up0, h[0][c], h[1][c]));
+                        fin(H - 1, c, P::pick3(h[H - 2][c], h[H - 1][c], dnl));
+                    }
+                }
                 if (__builtin_amdgcn_ballot_w64(changed != 0)) step_bits |= 1u << s;
-            }
-            if (s + 1 < busy) {
-                row_pass(0);
-                if constexpr (H > 1) row_pass(H - 1);
-                publish((s + 1) & 1);
+                if (s + 1 < busy) {
+                    row_pass_of(nxt, 0);
+                    if constexpr (H > 1) row_pass_of(nxt, H - 1);
+                    publish((s + 1) & 1);
 #pragma unroll
-                for (int j = 1; j < H - 1; ++j) row_pass(j);
+                    for (int j = 1; j < H - 1; ++j) row_pass_of(nxt, j);
+                }
+            };
+            int s = 0;
+            for (; s + 1 < busy; s += 2) {
+                step(s, v, v2);
+                step(s + 1, v2, v);
+            }
+            if (s < busy) {
+                step(s, v, v2);
+#pragma unroll
+                for (int j = 0; j < H; ++j)
+#pragma unroll
+                    for (int c = 0; c < CW; ++c) v[j][c] = v2[j][c];
             }
         }
     };
