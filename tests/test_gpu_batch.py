@@ -1,7 +1,9 @@
 """GPU parity of the batched persistent launch (gc_plan_*) against the CPU
 oracle, bit-exact per image, including graph replays, uneven sizes and
 chain lengths, in-place items, zero-step and empty items, both tile
-families and autotuned plans."""
+families, autotuned plans, an image beyond one launch grid, and items that
+run to stability (images and step counts against the oracle's
+reconstruction)."""
 import numpy as np
 import pytest
 import torch
