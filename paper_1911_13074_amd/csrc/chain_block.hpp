@@ -380,29 +380,98 @@ __device__ __forceinline__ uint32_t chain_block_body(const BlockArgs &a, int rx0
 #pragma unroll
         for (int r = 0; r < RPW; ++r) row_pass(r);
         publish(0);
-        for (int s = 0; s < busy; ++s) {
-            R nv[RPW][CW];
-            uint64_t changed = 0;
+        // (64-bit registers keep the one-step loop: the second state array
+        // costs them more in register pressure than the copies)
+        if constexpr (!D || sizeof(R) > 4) {
+            for (int s = 0; s < busy; ++s) {
+                R nv[RPW][CW];
+                uint64_t changed = 0;
 #pragma unroll
-            for (int r = 1; r < RPW - 1; ++r) column_pass(r, nv, changed);
-            // the edge rows, which wait for the exchange reads, after the
-            // middle rows, which cover the reads' latency
-            __builtin_amdgcn_sched_barrier(0);
-            column_pass(0, nv, changed);
-            if constexpr (RPW > 1) column_pass(RPW - 1, nv, changed);
+                for (int r = 1; r < RPW - 1; ++r) column_pass(r, nv, changed);
+                // the edge rows, which wait for the exchange reads, after the
+                // middle rows, which cover the reads' latency
+                __builtin_amdgcn_sched_barrier(0);
+                column_pass(0, nv, changed);
+                if constexpr (RPW > 1) column_pass(RPW - 1, nv, changed);
 #pragma unroll
-            for (int r = 0; r < RPW; ++r)
+                for (int r = 0; r < RPW; ++r)
 #pragma unroll
-                for (int c = 0; c < CW; ++c) v[r][c] = nv[r][c];
-            if constexpr (D) {
-                if (changed) step_bits |= 1u << s;
+                    for (int c = 0; c < CW; ++c) v[r][c] = nv[r][c];
+                if constexpr (D) {
+                    if (changed) step_bits |= 1u << s;
+                }
+                if (s + 1 < busy) {
+                    row_pass(0);
+                    if constexpr (RPW > 1) row_pass(RPW - 1);
+                    publish((s + 1) & 1);
+#pragma unroll
+                    for (int r = 1; r < RPW - 1; ++r) row_pass(r);
+                }
             }
-            if (s + 1 < busy) {
-                row_pass(0);
-                if constexpr (RPW > 1) row_pass(RPW - 1);
-                publish((s + 1) & 1);
+        } else {
+            // As in the packed body: two steps per iteration with the old and
+            // new states in alternating arrays, so the change test's reads of
+            // the old state need no register copies.
+            R v2[RPW][CW];
+            auto row_pass_of = [&](R (&st)[RPW][CW], int r) {
+                const R left = lane_shift<DPP_WAVE_SHR1>(st[r][CW - 1]);
+                const R right = lane_shift<DPP_WAVE_SHL1>(st[r][0]);
+                if constexpr (CW == 1) {
+                    h[r][0] = P::pick(P::pick(left, st[r][0]), right);
+                } else if constexpr (CW == 2) {
+                    const R t = P::pick(st[r][0], st[r][1]);
+                    h[r][0] = P::pick(t, left);
+                    h[r][1] = P::pick(t, right);
+                } else {
 #pragma unroll
-                for (int r = 1; r < RPW - 1; ++r) row_pass(r);
+                    for (int c = 0; c < CW; ++c) {
+                        const R l = c == 0 ? left : st[r][c - 1];
+                        const R rr = c == CW - 1 ? right : st[r][c + 1];
+                        h[r][c] = P::pick(P::pick(st[r][c], rr), l);
+                    }
+                }
+            };
+            auto step = [&](int s, R (&cur)[RPW][CW], R (&nxt)[RPW][CW]) {
+                uint64_t changed = 0;
+                auto col = [&](int r) {
+                    const int ry = w * RPW + r;
+                    const bool row_in_core = ry >= halo && ry < halo + a.core_y && ry0 + ry < a.height;
+#pragma unroll
+                    for (int c = 0; c < CW; ++c) {
+                        const R up = r == 0 ? above[c] : h[r - 1][c];
+                        const R dn = r == RPW - 1 ? below[c] : h[r + 1][c];
+                        R x = P::pick(P::pick(up, h[r][c]), dn);
+                        if constexpr (CLAMP) x = P::clamp(x, m[r][c]);
+                        const uint64_t row_mask = row_in_core ? ~0ull : 0ull;
+                        changed |= __builtin_amdgcn_ballot_w64(x != cur[r][c]) & col_in_core[c] & row_mask;
+                        nxt[r][c] = x;
+                    }
+                };
+#pragma unroll
+                for (int r = 1; r < RPW - 1; ++r) col(r);
+                __builtin_amdgcn_sched_barrier(0);
+                col(0);
+                if constexpr (RPW > 1) col(RPW - 1);
+                if (changed) step_bits |= 1u << s;
+                if (s + 1 < busy) {
+                    row_pass_of(nxt, 0);
+                    if constexpr (RPW > 1) row_pass_of(nxt, RPW - 1);
+                    publish((s + 1) & 1);
+#pragma unroll
+                    for (int r = 1; r < RPW - 1; ++r) row_pass_of(nxt, r);
+                }
+            };
+            int s = 0;
+            for (; s + 1 < busy; s += 2) {
+                step(s, v, v2);
+                step(s + 1, v2, v);
+            }
+            if (s < busy) {
+                step(s, v, v2);
+#pragma unroll
+                for (int r = 0; r < RPW; ++r)
+#pragma unroll
+                    for (int c = 0; c < CW; ++c) v[r][c] = v2[r][c];
             }
         }
     };
