@@ -36,6 +36,9 @@ PEAK_TCMP = 256 * 64 * 2.4e9 * 4 / 1e12   # 157.29 T compare-selects / s
 # HBM3E 8 TB/s; LDS 128 bytes per clock per CU.
 PEAK_HBM_GB_S = 8000
 PEAK_LDS_TB_S = 256 * 128 * 2.4e9 / 1e12   # 78.64 TB/s
+# Side of the output tile ("core") of one workgroup in the headline launch
+# shape (128 x 128 regions, 32-step halo).
+CORE_SIDE = 64
 CMP_PER_PX_STEP_GEODESIC = 5
 CMP_PER_PX_STEP_PLAIN = 4
 
@@ -90,7 +93,10 @@ def kernel_profile(fn, steps):
 
 PROFILE = os.path.join(ROOT, "profiles", "chain_u8_1024_geodesic_dilation.md")
 PROFILE_SQ = os.path.join(ROOT, "profiles", "chain_u8_1024_sq_counters.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1911_13074_amd", "csrc", "chain_block.hpp")]
+# The profiled kernel's code and its launch shape (tile families, steps per
+# launch, grid): a change to either makes the committed counters stale.
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1911_13074_amd", "csrc", f)
+                  for f in ("chain_block.hpp", "geochain.hip")]
 
 
 def profiled_traffic():
@@ -164,10 +170,10 @@ def verify(S, N, F, M, f, m, headline_ref, dev, with_extra=True, batch_outs=None
     """Bitwise parity with the oracle of what the run measured: each GPU
     result is computed once more, untimed, and compared element by element
     (and by step count where there is one).  The headline's oracle result is
-    the CPU baseline's own.  Of the batch every 16th image is checked, of the
-    batched reconstruction every 4th (image and step count); the
-    gradient's parity is left to the test suite (its oracle takes minutes
-    at this size).  The batch's images are those of the timed plan's last
+    the CPU baseline's own.  Every image of the batch is checked, and every
+    image and step count of the batched reconstruction; the gradient's
+    parity is left to the test suite (its oracle takes about a minute at
+    this size).  The batch's images are those of the timed plan's last
     replay."""
     import oracle
     import paper_1911_13074_amd as gc
@@ -223,7 +229,7 @@ def verify(S, N, F, M, f, m, headline_ref, dev, with_extra=True, batch_outs=None
             gc.set_window_path(0)
     if batch_outs:
         items = workloads.batch_u8().items
-        ok["batched_64_uneven_u8_every_16th"] = all(
+        ok["batched_64_uneven_u8_every_image"] = len(batch_outs) == len(items) and all(
             bool(np.array_equal(o, oracle.chain(oracle.DILATE, items[i].marker, items[i].n_steps, items[i].mask)))
             for i, o in batch_outs.items())
     if rec_batch_outs:
@@ -232,7 +238,7 @@ def verify(S, N, F, M, f, m, headline_ref, dev, with_extra=True, batch_outs=None
         for i, (o, st_) in rec_batch_outs.items():
             r, rs, _ = oracle.reconstruct(oracle.DILATE, items[i].marker, items[i].mask)
             good = good and bool(np.array_equal(o, r)) and st_ == rs
-        ok["batched_reconstruction_16_u8_every_4th"] = good
+        ok["batched_reconstruction_16_u8_every_image"] = good and len(rec_batch_outs) == 16
     return ok
 
 
@@ -317,6 +323,22 @@ def main():
         "rocprof_avg_dispatch_ms": round(prof_ms, 5) if prof_ms else None,
         "algorithmic_bytes_per_launch": 3 * px,
     }
+    # The memory roof the target is stated against: the lower of the HBM
+    # roof at the chosen steps per launch k with T x T cores, where fused
+    # traffic is s (2 (1 + 2k/T)^2 + 1) / k bytes per pixel-step (read state
+    # and mask over the region, write the core), and the LDS roof of a
+    # whole-state exchange, 2s bytes per pixel-step (s = 1 byte for u8).
+    k_launch = max(1, int(round(steps_per_launch)))
+    core = CORE_SIDE
+    hbm_b = (2 * (1 + 2 * k_launch / core) ** 2 + 1) / k_launch
+    hbm_roof = PEAK_HBM_GB_S * 1e9 / hbm_b / 1e9
+    lds_roof = PEAK_LDS_TB_S * 1e12 / 2.0 / 1e9
+    roof = min(hbm_roof, lds_roof)
+    roofline["memory_roof"] = {
+        "gpx_steps_per_s": round(roof, 1), "binding": "hbm" if hbm_roof <= lds_roof else "lds",
+        "hbm_roof_gpx_steps_per_s": round(hbm_roof, 1), "hbm_bytes_per_px_step": round(hbm_b, 4),
+        "lds_roof_gpx_steps_per_s": round(lds_roof, 1), "core_side": core, "k": k_launch,
+        "frac": round(value / roof, 4), "target_frac": 0.5, "target_met": bool(value / roof >= 0.5)}
     # Context beside the ALU bound: the kernel's HBM rate (profiled bytes
     # per dispatch over the average launch) and its LDS exchange rate (bytes
     # per dispatch from the profiled LDS instruction count).
@@ -421,7 +443,7 @@ def main():
             "tile_family": info["tile"], "block_steps": info["block_steps"], "workgroups": info["workgroups"],
             "builtin_plan_gpx_steps_per_s": round(batch.px_steps / ms_d / 1e6, 2)}
         torch.cuda.synchronize()
-        batch_outs = {i: plan.outs[i].cpu().numpy() for i in range(0, len(items), 16)}
+        batch_outs = {i: plan.outs[i].cpu().numpy() for i in range(len(items))}
         plan.close()
         del items
         # Batched reconstruction: the first 16 images of that batch run to
@@ -446,7 +468,7 @@ def main():
             "vs_single_image_calls": round(ms_rs / ms_rb, 3),
             "gpx_steps_per_s": round(px_rb / ms_rb / 1e6, 2), "steps_min_max": [min(rsteps), max(rsteps)]}
         torch.cuda.synchronize()
-        rec_batch_outs = {i: (rplan.outs[i].cpu().numpy(), rsteps[i]) for i in range(0, len(rec_items), 4)}
+        rec_batch_outs = {i: (rplan.outs[i].cpu().numpy(), rsteps[i]) for i in range(len(rec_items))}
         rplan.close()
         del rec_items, rec_outs
         # Differentiable: 16 x 1024^2 f32, 200 steps, forward + backward.
@@ -473,13 +495,14 @@ def main():
         _, codes = gc.geodesic_chain_fwd_codes("dilate", Fd, Md, 32)
         gm = torch.zeros_like(Md)
         c_ms, c_n, c_st = kernel_profile(lambda: gc.geodesic_chain_fwd_codes("dilate", Fd, Md, 32, codes=codes), 2)
-        b_ms, b_n, b_st = kernel_profile(lambda: gc.geodesic_chain_bwd(codes, Gd, gm), 2)
+        b_ms, b_n, b_st = kernel_profile(lambda: gc.geodesic_chain_bwd("dilate", codes, Gd, gm), 2)
         npx = Fd.numel()
         k_c, k_b = c_st / max(c_n, 1), b_st / max(b_n, 1)
         extra["fwd_bwd_16x1024_f32_200"] = {
             "gpx_steps_per_s": round(px_d / ms_fb / 1e6, 2), "ms": round(ms_fb, 3),
             "forward_only_gpx_steps_per_s": round(px_d / ms_fo / 1e6, 2),
-            "vs_plain": round(px_d / ms_fb / 1e6 / value, 4), "checkpoint_every": 32,
+            "vs_plain": round(px_d / ms_fb / 1e6 / value, 4),
+            "vs_f32_forward": round(ms_fo / ms_fb, 4), "checkpoint_every": 32,
             "codes_kernel": {"avg_launch_ms": round(c_ms, 4), "steps_per_launch": round(k_c, 2),
                              "gpx_steps_per_s": round(npx * k_c / (c_ms * 1e-3) / 1e9, 1),
                              "hbm_gb_s": round((12 + k_c) * npx / (c_ms * 1e-3) / 1e9, 1), "peak_gb_s": 8000},
@@ -548,7 +571,9 @@ def main():
     if "batched_64_uneven_u8" in extra:
         # the metric's two ratios: each workload's rate over the plain chain's
         line["vs_plain"] = {"batched_64_uneven_u8": extra["batched_64_uneven_u8"]["vs_plain"],
-                            "fwd_bwd_16x1024_f32_200": extra["fwd_bwd_16x1024_f32_200"]["vs_plain"]}
+                            "fwd_bwd_16x1024_f32_200": extra["fwd_bwd_16x1024_f32_200"]["vs_plain"],
+                            "fwd_bwd_16x1024_f32_200_vs_f32_forward":
+                                extra["fwd_bwd_16x1024_f32_200"]["vs_f32_forward"]}
     line["extra"] = extra
     print(json.dumps(line), flush=True)
     if "parity" in line and not all(line["parity"].values()):

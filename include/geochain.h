@@ -47,13 +47,21 @@
  *     validated before any HIP call; on error nothing is enqueued.
  *     gc_last_error() gives a detail message for the calling thread.
  *   - Calls that run concurrently on different streams are safe; each
- *     (device, stream) pair has its own workspace.
+ *     (device, stream) pair has its own workspace.  The exception is
+ *     gc_plan_launch: two plans whose launches run at the same time on
+ *     different streams are not supported (see the batch section).
  *   - The chain entry points (geodesic and plain) may be recorded into a
  *     HIP graph by stream capture once a call of at least the same size has
  *     run on the capturing stream (that call sizes the stream's workspace;
- *     a capture that would have to grow it fails).  Entry points that read
- *     a convergence word on the host (reconstructions, the operators built
- *     on them, the quasi-distance transform) cannot be captured.
+ *     a capture that would have to grow it returns GC_ERR_UNSUPPORTED).
+ *     The graph keeps using the capturing stream's workspace: replays must
+ *     not run at the same time as library calls on that stream (replaying
+ *     on the capturing stream itself orders them).  A workspace that a
+ *     capture has used is never freed: when a later call on that stream
+ *     needs a larger one, the old buffer stays allocated until the process
+ *     ends, so replays stay valid.  Entry points that read a convergence
+ *     word on the host (reconstructions, the operators built on them, the
+ *     quasi-distance transform) cannot be captured.
  */
 #ifndef GEOCHAIN_H
 #define GEOCHAIN_H
@@ -250,6 +258,13 @@ int gc_quasi_distance(gc_dtype dtype, const void *f, int32_t *dist, void *residu
  *
  * gc_plan_launch replays the graph on hip_stream (asynchronous).  Launches
  * of one plan must not overlap each other (they share the workspace).
+ * The kernel's workgroups wait for each other, so it needs all of its grid
+ * resident on the device at once (the grid is sized to what the device
+ * holds when nothing else runs): launches of two plans at the same time on
+ * different streams, or beside long-running kernels of other work, are not
+ * supported.  Such a launch does not hang: a wait that cannot finish gives
+ * up after a bounded time and gc_plan_status reports GC_ERR_HIP (results
+ * invalid).
  * With run-to-stability items it is synchronous instead: each replay runs
  * every active image for 4 blocks of 20 steps while the kernel records, per
  * block, which steps changed a pixel; between replays the host retires the
@@ -335,6 +350,9 @@ int gc_autotune_clear(void);
  * gathers the gradients of the neighbours whose codes point at it, visiting
  * them in raster order (the same order in which a raster-order scatter
  * would deliver them).  grad_marker must not overlap grad_out or grad_mask.
+ * op names the chain the codes were recorded for (GC_DILATE or GC_ERODE,
+ * else GC_ERR_INVALID_ARG); the codes already say which input each value
+ * came from, so the arithmetic of the reverse pass is the same for both.
  *
  * Batches: n_images images of one shape, image i at element offset
  * i * image_stride from each image pointer (image_stride >= (height - 1) *
@@ -344,7 +362,7 @@ int gc_autotune_clear(void);
 int gc_geodesic_chain_fwd_codes(gc_dtype dtype, gc_op op, const void *marker, const void *mask,
                                 void *out, uint8_t *codes, gc_shape shape, int32_t n_images,
                                 int64_t image_stride, int64_t n_steps, void *hip_stream);
-int gc_geodesic_chain_bwd(gc_dtype dtype, const uint8_t *codes, const void *grad_out,
+int gc_geodesic_chain_bwd(gc_dtype dtype, gc_op op, const uint8_t *codes, const void *grad_out,
                           void *grad_marker, void *grad_mask, gc_shape shape, int32_t n_images,
                           int64_t image_stride, int64_t n_steps, void *hip_stream);
 

@@ -8,7 +8,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgeochain.so")
+# GEOCHAIN_LIB names another build of the same library (the tests load a
+# host-sanitizer build through it); by default the in-tree build.
+LIB_PATH = os.environ.get("GEOCHAIN_LIB") or os.path.join(_HERE, "libgeochain.so")
 
 GC_U8, GC_F32, GC_F64 = 0, 1, 2
 GC_DILATE, GC_ERODE = 0, 1
@@ -80,7 +82,7 @@ SIGNATURES = {
     "gc_autotune_clear": (ctypes.c_int, []),
     "gc_geodesic_chain_fwd_codes": (ctypes.c_int, [_DT, _DT, _VP, _VP, _VP, _VP, gc_shape, _I32, _I64,
                                                    _I64, _VP]),
-    "gc_geodesic_chain_bwd": (ctypes.c_int, [_DT, _VP, _VP, _VP, _VP, gc_shape, _I32, _I64, _I64, _VP]),
+    "gc_geodesic_chain_bwd": (ctypes.c_int, [_DT, _DT, _VP, _VP, _VP, _VP, gc_shape, _I32, _I64, _I64, _VP]),
     "gc_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "gc_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), _P_I64, _P_I64]),
 }

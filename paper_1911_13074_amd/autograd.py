@@ -49,7 +49,7 @@ class GeodesicChainFunction(torch.autograd.Function):
         for i in reversed(range(len(starts))):
             n = min(ctx.seg, ctx.n_steps - starts[i])
             _, codes = ops.geodesic_chain_fwd_codes(ctx.op, ckpts[i], mask, n)
-            g = ops.geodesic_chain_bwd(codes, g, gm)
+            g = ops.geodesic_chain_bwd(ctx.op, codes, g, gm)
             del codes
         return g, gm, None, None, None
 

@@ -15,8 +15,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     # min/max over values that are never NaN: lets v_max3/v_min3 take the
-    # operands without canonicalising them first.
-    "-fno-honor-nans",
+    # operands without canonicalising them first.  Device code only: the
+    # host code tests arguments for NaN.
+    "-Xarch_device", "-fno-honor-nans",
     # keep the backend from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",

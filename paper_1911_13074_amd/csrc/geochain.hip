@@ -42,12 +42,39 @@ static int fail(int status, const char *fmt, ...) {
     return status;
 }
 
+// Fault injection for tests of the error path: with the environment
+// variable GEOCHAIN_INJECT_HIP_FAULT set to some text, every checked HIP
+// call (GC_HIP below) whose source text contains it is not made and fails
+// with GC_ERR_HIP instead.  Read once, at the first checked call.
+static const char *inject_pattern() {
+    static const char *p = [] {
+        const char *e = getenv("GEOCHAIN_INJECT_HIP_FAULT");
+        return (e && *e) ? e : (const char *)nullptr;
+    }();
+    return p;
+}
+
+static bool inject_fault(const char *call_text) {
+    const char *p = inject_pattern();
+    return p != nullptr && strstr(call_text, p) != nullptr;
+}
+
 #define GC_HIP(call)                                                              \
     do {                                                                          \
+        if (inject_fault(#call))                                                  \
+            return fail(GC_ERR_HIP, "%s failed: injected fault", #call);          \
         hipError_t e_ = (call);                                                   \
         if (e_ != hipSuccess)                                                     \
             return fail(GC_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
     } while (0)
+
+// Finite test on the bit pattern (exponent not all ones), which no
+// floating-point option of the compiler can fold away.
+static bool finite_bits(double v) {
+    uint64_t b;
+    memcpy(&b, &v, sizeof b);
+    return ((b >> 52) & 0x7FFu) != 0x7FFu;
+}
 
 static size_t elem_size(gc_dtype d) {
     switch (d) {
@@ -208,30 +235,68 @@ struct Workspace {
     void *partials = nullptr;       // PARTIALS_MAX per-workgroup extrema (operators)
     void *buf2 = nullptr;           // images of composed operators (granulometry)
     size_t bytes2 = 0;
+    // A HIP graph recorded by stream capture keeps the addresses of buf and
+    // buf2 as they were during the capture.  Once a capture has used them
+    // they are never freed: when a later call needs more room, the old
+    // buffer is retired (kept allocated until the process ends) and a new
+    // one takes its place, so replays never touch freed memory.
+    bool captured = false;
+    bool captured2 = false;
 };
 
 static std::mutex g_ws_mu;
 static std::map<std::pair<int, void *>, Workspace> g_ws;
+static std::vector<void *> g_retired;   // buffers a recorded graph may still use
+
+// Whether work enqueued on the stream now is being recorded into a graph.
+static int stream_capturing(void *stream, bool *capturing) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    GC_HIP(hipStreamIsCapturing((hipStream_t)stream, &cs));
+    *capturing = cs != hipStreamCaptureStatusNone;
+    return GC_OK;
+}
+
+// Replaces a workspace buffer that must grow: freed after the stream's work
+// is done, or retired if a capture has used it.
+static int grow_release(void *stream, void **buf, size_t *bytes, bool *captured, bool capturing) {
+    if (capturing)
+        return fail(GC_ERR_UNSUPPORTED, "the stream's workspace would have to grow during stream capture "
+                                        "(%zu bytes now); make an uncaptured call of this size first", *bytes);
+    if (!*buf) return GC_OK;
+    if (*captured) {
+        g_retired.push_back(*buf);
+    } else {
+        GC_HIP(hipStreamSynchronize((hipStream_t)stream));
+        GC_HIP(hipFree(*buf));
+    }
+    *buf = nullptr;
+    *bytes = 0;
+    *captured = false;
+    return GC_OK;
+}
 
 static int get_workspace(void *stream, size_t bytes, size_t nwords, Workspace **out) {
     int dev = 0;
     GC_HIP(hipGetDevice(&dev));
+    bool capturing = false;
+    {
+        const int rc = stream_capturing(stream, &capturing);
+        if (rc != GC_OK) return rc;
+    }
     std::lock_guard<std::mutex> g(g_ws_mu);
     Workspace &w = g_ws[{dev, stream}];
     if (w.bytes < bytes) {
-        if (w.buf) {
-            GC_HIP(hipStreamSynchronize((hipStream_t)stream));
-            GC_HIP(hipFree(w.buf));
-            w.buf = nullptr;
-            w.bytes = 0;
-        }
+        const int rc = grow_release(stream, &w.buf, &w.bytes, &w.captured, capturing);
+        if (rc != GC_OK) return rc;
         if (hipMalloc(&w.buf, bytes) != hipSuccess) {
             (void)hipGetLastError();
             return fail(GC_ERR_NO_MEMORY, "workspace of %zu bytes", bytes);
         }
         w.bytes = bytes;
     }
+    if (capturing && bytes > 0) w.captured = true;
     if (w.nwords < nwords) {
+        if (capturing) return fail(GC_ERR_UNSUPPORTED, "change words cannot be allocated during stream capture");
         if (w.words) {
             GC_HIP(hipStreamSynchronize((hipStream_t)stream));
             GC_HIP(hipFree(w.words));
@@ -279,21 +344,23 @@ static int get_partials(void *stream, void **out) {
 static int get_buf2(void *stream, size_t bytes, void **out) {
     int dev = 0;
     GC_HIP(hipGetDevice(&dev));
+    bool capturing = false;
+    {
+        const int rc = stream_capturing(stream, &capturing);
+        if (rc != GC_OK) return rc;
+    }
     std::lock_guard<std::mutex> g(g_ws_mu);
     Workspace &w = g_ws[{dev, stream}];
     if (w.bytes2 < bytes) {
-        if (w.buf2) {
-            GC_HIP(hipStreamSynchronize((hipStream_t)stream));
-            GC_HIP(hipFree(w.buf2));
-            w.buf2 = nullptr;
-            w.bytes2 = 0;
-        }
+        const int rc = grow_release(stream, &w.buf2, &w.bytes2, &w.captured2, capturing);
+        if (rc != GC_OK) return rc;
         if (hipMalloc(&w.buf2, bytes) != hipSuccess) {
             (void)hipGetLastError();
             return fail(GC_ERR_NO_MEMORY, "operator workspace of %zu bytes", bytes);
         }
         w.bytes2 = bytes;
     }
+    if (capturing && bytes > 0) w.captured2 = true;
     *out = w.buf2;
     return GC_OK;
 }
@@ -592,8 +659,12 @@ static int run_window(gc_dtype dtype, int op, const void *in, void *out, const g
 // ---------------------------------------------------------------------------
 // fixed-length chains
 // ---------------------------------------------------------------------------
+// fixed_ws: a caller-chosen work buffer of fixed_bytes bytes in place of
+// the stream's workspace (the entry point that allocates nothing); such
+// calls also skip the measurement hook, whose events are allocated.
 static int run_chain(gc_dtype dtype, int op, int mode, const void *src, const void *mask, void *out,
-                     const gc_shape &s, int64_t n, void *stream) {
+                     const gc_shape &s, int64_t n, void *stream, void *fixed_ws = nullptr,
+                     size_t fixed_bytes = 0) {
     if (n < 0) return fail(GC_ERR_INVALID_ARG, "n_steps < 0");
     const bool empty = s.width == 0 || s.height == 0;
     const size_t es = elem_size(dtype);
@@ -603,38 +674,53 @@ static int run_chain(gc_dtype dtype, int op, int mode, const void *src, const vo
     if (mode == MODE_PLAIN && window_path(dtype, s, n)) return run_window(dtype, op, src, out, s, n, stream);
 
     const Plan1 p = choose_plan(s, n, false);
-    // launches: L-1 of p.k steps and a last one with the remainder
-    std::vector<int> ks;
-    for (int64_t left = n; left > 0; left -= p.k) ks.push_back((int)std::min<int64_t>(p.k, left));
-    // In place with an odd number of launches would make the first launch
-    // write the buffer it reads: split the first launch (or copy first).
-    bool copy_first = false;
-    if (src == out && (ks.size() % 2 == 1)) {
-        if (ks[0] >= 2) {
-            const int a = ks[0] / 2;
-            ks.insert(ks.begin(), a);
-            ks[1] -= a;
-        } else {
-            copy_first = true;
-        }
+    // Launches: L0 - 1 of p.k steps and a last one with the remainder.  In
+    // place with an odd number of launches would make the first launch
+    // write the buffer it reads: split the first launch in two (or, if it
+    // is a single step, copy first).  Computed per launch, with no list.
+    const int64_t L0 = (n + p.k - 1) / p.k;
+    const int k0 = (int)std::min<int64_t>(p.k, n);
+    bool split = false, copy_first = false;
+    if (src == out && L0 % 2 == 1) {
+        if (k0 >= 2) split = true;
+        else copy_first = true;
     }
-    Workspace *ws = nullptr;
+    const int64_t L = L0 + (split ? 1 : 0);
+    auto k_of = [&](int64_t i) -> int {
+        if (split) {
+            if (i == 0) return k0 / 2;
+            if (i == 1) return k0 - k0 / 2;
+            i -= 1;
+        }
+        return (int)std::min<int64_t>(p.k, n - i * p.k);
+    };
     const size_t bytes = (size_t)((s.height - 1) * s.pitch + s.width) * es;
-    int rc = get_workspace(stream, bytes, 0, &ws);
-    if (rc != GC_OK) return rc;
+    void *work = fixed_ws;
+    if (fixed_ws) {
+        if (bytes > fixed_bytes)
+            return fail(GC_ERR_UNSUPPORTED, "image needs %zu bytes of work buffer, the fixed one holds %zu", bytes,
+                        fixed_bytes);
+    } else {
+        Workspace *ws = nullptr;
+        const int rc = get_workspace(stream, bytes, 0, &ws);
+        if (rc != GC_OK) return rc;
+        work = ws->buf;
+    }
+    const bool hook = fixed_ws == nullptr;
 
     const void *cur = src;
     if (copy_first) {
-        rc = copy_image(ws->buf, src, s, es, st);
+        const int rc = copy_image(work, src, s, es, st);
         if (rc != GC_OK) return rc;
-        cur = ws->buf;
-        // now reading from ws: the single launch writes out
+        cur = work;
     }
-    const size_t L = ks.size();
-    for (size_t i = 0; i < L; ++i) {
-        void *dst = ((L - 1 - i) % 2 == 0) ? out : ws->buf;
-        if (copy_first) dst = out;  // L == 1 here
-        const Geometry g = geometry(s, p.fam, ks[i]);
+    for (int64_t i = 0; i < L; ++i) {
+        const int ki = k_of(i);
+        // the last launch writes out; after a copy into the work buffer the
+        // first launch reads it, and the alternation never writes the
+        // buffer a launch reads
+        void *dst = ((L - 1 - i) % 2 == 0) ? out : work;
+        const Geometry g = geometry(s, p.fam, ki);
         BlockArgs a{};
         a.src = cur;
         a.mask = mask;
@@ -642,15 +728,15 @@ static int run_chain(gc_dtype dtype, int op, int mode, const void *src, const vo
         a.width = (int32_t)s.width;
         a.height = (int32_t)s.height;
         a.pitch = s.pitch;
-        a.k = ks[i];
-        a.halo = ks[i];
+        a.k = ki;
+        a.halo = ki;
         a.core_x = g.core_x;
         a.core_y = g.core_y;
         a.tiles_x = g.tiles_x;
         LaunchFn fn = pick_launch(dtype, op, mode, false, p.fam);
-        const int pr = prof_begin(st, ks[i]);
+        const int pr = hook ? prof_begin(st, ki) : -1;
         fn(a, g.tiles, st);
-        prof_end(pr, st);
+        if (hook) prof_end(pr, st);
         GC_HIP(hipGetLastError());
         cur = dst;
     }
@@ -1732,6 +1818,37 @@ static int run_bwd(gc_dtype dtype, const uint8_t *codes, const void *g_out, void
 
 using namespace geochain;
 
+// Enum arguments arrive from C callers, where any int is a valid value of
+// the type; in C++ reading an out-of-range value through the enum type is
+// undefined.  Entry points therefore look at the bits first (through
+// memcpy, which reads no enum) and refuse unknown values before the
+// argument is used.
+template <typename E>
+static int enum_bits(const E *e) {
+    static_assert(sizeof(E) == sizeof(int), "C enums are int-sized here");
+    int v;
+    memcpy(&v, e, sizeof v);
+    return v;
+}
+
+#define GC_CHECK_DTYPE(d)                                                                   \
+    do {                                                                                    \
+        const int v_ = enum_bits(&(d));                                                     \
+        if (v_ != GC_U8 && v_ != GC_F32 && v_ != GC_F64) {                                  \
+            g_last_error.clear();                                                           \
+            return fail(GC_ERR_INVALID_ARG, "unknown dtype %d", v_);                        \
+        }                                                                                   \
+    } while (0)
+#define GC_CHECK_OP(o)                                                                      \
+    do {                                                                                    \
+        const int v_ = enum_bits(&(o));                                                     \
+        if (v_ != GC_DILATE && v_ != GC_ERODE) {                                            \
+            g_last_error.clear();                                                           \
+            return fail(GC_ERR_INVALID_ARG, "unknown op %d", v_);                           \
+        }                                                                                   \
+    } while (0)
+
+
 template <typename T>
 static int run_value_scan_t(const T *img, const gc_shape &s, uint32_t *found, void *stream) {
     hipStream_t st = (hipStream_t)stream;
@@ -1787,11 +1904,13 @@ static int geodesic_chain(gc_dtype dtype, int op, const void *marker, const void
 
 int gc_geodesic_dilate_chain(gc_dtype dtype, const void *marker, const void *mask, void *out,
                              gc_shape shape, int64_t n_steps, void *hip_stream) {
+    GC_CHECK_DTYPE(dtype);
     return geodesic_chain(dtype, OP_DILATE, marker, mask, out, shape, n_steps, hip_stream);
 }
 
 int gc_geodesic_erode_chain(gc_dtype dtype, const void *marker, const void *mask, void *out,
                             gc_shape shape, int64_t n_steps, void *hip_stream) {
+    GC_CHECK_DTYPE(dtype);
     return geodesic_chain(dtype, OP_ERODE, marker, mask, out, shape, n_steps, hip_stream);
 }
 
@@ -1806,11 +1925,13 @@ static int plain_chain(gc_dtype dtype, int op, const void *in, void *out, gc_sha
 
 int gc_dilate_chain(gc_dtype dtype, const void *in, void *out, gc_shape shape, int64_t n_steps,
                     void *hip_stream) {
+    GC_CHECK_DTYPE(dtype);
     return plain_chain(dtype, OP_DILATE, in, out, shape, n_steps, hip_stream);
 }
 
 int gc_erode_chain(gc_dtype dtype, const void *in, void *out, gc_shape shape, int64_t n_steps,
                    void *hip_stream) {
+    GC_CHECK_DTYPE(dtype);
     return plain_chain(dtype, OP_ERODE, in, out, shape, n_steps, hip_stream);
 }
 
@@ -1827,12 +1948,14 @@ static int reconstruct(gc_dtype dtype, int op, const void *marker, const void *m
 int gc_reconstruct_by_dilation(gc_dtype dtype, const void *marker, const void *mask, void *out,
                                gc_shape shape, int64_t max_steps, int64_t *steps_out,
                                void *hip_stream) {
+    GC_CHECK_DTYPE(dtype);
     return reconstruct(dtype, OP_DILATE, marker, mask, out, shape, max_steps, steps_out, hip_stream);
 }
 
 int gc_reconstruct_by_erosion(gc_dtype dtype, const void *marker, const void *mask, void *out,
                               gc_shape shape, int64_t max_steps, int64_t *steps_out,
                               void *hip_stream) {
+    GC_CHECK_DTYPE(dtype);
     return reconstruct(dtype, OP_ERODE, marker, mask, out, shape, max_steps, steps_out, hip_stream);
 }
 
@@ -1848,7 +1971,7 @@ static int geodesic_operator(gc_dtype dtype, int which, const void *f, void *out
     if (!empty && overlap(extent(out, shape, es), extent(f, shape, es)))
         return fail(GC_ERR_ALIAS, "out overlaps f (f is the mask of the reconstruction)");
     if (which == GOP_HMAX || which == GOP_DOME) {
-        if (!std::isfinite(h) || h < 0) return fail(GC_ERR_INVALID_ARG, "h must be finite and >= 0");
+        if (!finite_bits(h) || h < 0) return fail(GC_ERR_INVALID_ARG, "h must be finite and >= 0");
         if (dtype == GC_U8 && h != std::floor(h))
             return fail(GC_ERR_INVALID_ARG, "h must be an integer for u8 images");
     }
@@ -1870,32 +1993,38 @@ static int geodesic_operator(gc_dtype dtype, int which, const void *f, void *out
 
 int gc_hmax(gc_dtype dtype, const void *f, void *out, gc_shape shape, double h, int64_t max_steps,
             int64_t *steps_out, void *hip_stream) {
+    GC_CHECK_DTYPE(dtype);
     return geodesic_operator(dtype, GOP_HMAX, f, out, shape, h, 0, max_steps, steps_out, hip_stream);
 }
 
 int gc_dome(gc_dtype dtype, const void *f, void *out, gc_shape shape, double h, int64_t max_steps,
             int64_t *steps_out, void *hip_stream) {
+    GC_CHECK_DTYPE(dtype);
     return geodesic_operator(dtype, GOP_DOME, f, out, shape, h, 0, max_steps, steps_out, hip_stream);
 }
 
 int gc_hfill(gc_dtype dtype, const void *f, void *out, gc_shape shape, int64_t max_steps,
              int64_t *steps_out, void *hip_stream) {
+    GC_CHECK_DTYPE(dtype);
     return geodesic_operator(dtype, GOP_HFILL, f, out, shape, 0.0, 0, max_steps, steps_out, hip_stream);
 }
 
 int gc_raobj(gc_dtype dtype, const void *f, void *out, gc_shape shape, int64_t max_steps,
              int64_t *steps_out, void *hip_stream) {
+    GC_CHECK_DTYPE(dtype);
     return geodesic_operator(dtype, GOP_RAOBJ, f, out, shape, 0.0, 0, max_steps, steps_out, hip_stream);
 }
 
 int gc_open_by_reconstruction(gc_dtype dtype, const void *f, void *out, gc_shape shape, int64_t size,
                               int64_t max_steps, int64_t *steps_out, void *hip_stream) {
+    GC_CHECK_DTYPE(dtype);
     return geodesic_operator(dtype, GOP_OPEN_REC, f, out, shape, 0.0, size, max_steps, steps_out,
                              hip_stream);
 }
 
 int gc_granulometry(gc_dtype dtype, const void *f, gc_shape shape, int32_t s_max, double *G, double *PS,
                     void *hip_stream) {
+    GC_CHECK_DTYPE(dtype);
     g_last_error.clear();
     int rc = validate_shape(dtype, shape);
     if (rc != GC_OK) return rc;
@@ -1918,6 +2047,7 @@ int gc_granulometry(gc_dtype dtype, const void *f, gc_shape shape, int32_t s_max
 }
 
 int gc_asf(gc_dtype dtype, const void *f, void *out, gc_shape shape, int32_t s_max, void *hip_stream) {
+    GC_CHECK_DTYPE(dtype);
     g_last_error.clear();
     int rc = validate_images(dtype, f, nullptr, out, shape);
     if (rc != GC_OK) return rc;
@@ -1928,6 +2058,7 @@ int gc_asf(gc_dtype dtype, const void *f, void *out, gc_shape shape, int32_t s_m
 
 int gc_quasi_distance(gc_dtype dtype, const void *f, int32_t *dist, void *residual, gc_shape shape,
                       int32_t lipschitz, int64_t *erosion_steps, int64_t *eta_steps, void *hip_stream) {
+    GC_CHECK_DTYPE(dtype);
     g_last_error.clear();
     if (erosion_steps) *erosion_steps = 0;
     if (eta_steps) *eta_steps = 0;
@@ -1961,6 +2092,8 @@ int gc_quasi_distance(gc_dtype dtype, const void *f, int32_t *dist, void *residu
 int gc_geodesic_chain_fwd_codes(gc_dtype dtype, gc_op op, const void *marker, const void *mask, void *out,
                                 uint8_t *codes, gc_shape shape, int32_t n_images, int64_t image_stride,
                                 int64_t n_steps, void *hip_stream) {
+    GC_CHECK_DTYPE(dtype);
+    GC_CHECK_OP(op);
     g_last_error.clear();
     int rc = validate_batch(dtype, shape, n_images, image_stride, n_steps);
     if (rc != GC_OK) return rc;
@@ -1978,12 +2111,15 @@ int gc_geodesic_chain_fwd_codes(gc_dtype dtype, gc_op op, const void *marker, co
                          (hipStream_t)hip_stream);
 }
 
-int gc_geodesic_chain_bwd(gc_dtype dtype, const uint8_t *codes, const void *grad_out, void *grad_marker,
-                          void *grad_mask, gc_shape shape, int32_t n_images, int64_t image_stride, int64_t n_steps,
-                          void *hip_stream) {
+int gc_geodesic_chain_bwd(gc_dtype dtype, gc_op op, const uint8_t *codes, const void *grad_out,
+                          void *grad_marker, void *grad_mask, gc_shape shape, int32_t n_images,
+                          int64_t image_stride, int64_t n_steps, void *hip_stream) {
+    GC_CHECK_DTYPE(dtype);
+    GC_CHECK_OP(op);
     g_last_error.clear();
     int rc = validate_batch(dtype, shape, n_images, image_stride, n_steps);
     if (rc != GC_OK) return rc;
+    if (op != GC_DILATE && op != GC_ERODE) return fail(GC_ERR_INVALID_ARG, "unknown op");
     const bool empty = shape.width == 0 || shape.height == 0 || n_images == 0;
     if (empty) return GC_OK;
     if (!grad_out || !grad_marker || !grad_mask || (n_steps > 0 && !codes))
@@ -1998,6 +2134,8 @@ int gc_geodesic_chain_bwd(gc_dtype dtype, const uint8_t *codes, const void *grad
 }
 
 int gc_plan_create(gc_dtype dtype, gc_op op, const gc_item *items, int32_t n_items, gc_plan **plan_out) {
+    GC_CHECK_DTYPE(dtype);
+    GC_CHECK_OP(op);
     g_last_error.clear();
     return plan_build(dtype, (int)op, items, n_items, plan_out, nullptr);
 }
@@ -2190,6 +2328,8 @@ int gc_plan_destroy(gc_plan *plan) {
 
 int gc_autotune(gc_dtype dtype, gc_op op, int32_t geodesic, int64_t width, int64_t height, int32_t *best_tile,
                 int32_t *best_k) {
+    GC_CHECK_DTYPE(dtype);
+    GC_CHECK_OP(op);
     g_last_error.clear();
     if (elem_size(dtype) == 0) return fail(GC_ERR_INVALID_ARG, "unknown dtype");
     if (op != GC_DILATE && op != GC_ERODE) return fail(GC_ERR_INVALID_ARG, "unknown op");
@@ -2243,6 +2383,7 @@ int gc_profile_read(double *kernel_ms, int64_t *launches, int64_t *steps) {
 }
 
 int gc_validate_values(gc_dtype dtype, const void *image, gc_shape shape, int32_t allow_inf, void *hip_stream) {
+    GC_CHECK_DTYPE(dtype);
     g_last_error.clear();
     int rc = validate_shape(dtype, shape);
     if (rc != GC_OK) return rc;

@@ -353,9 +353,10 @@ def autotune_clear():
 
 
 def _batch_view(t: torch.Tensor, name: str):
-    """(B, H, W) or (H, W) device tensor -> (tensor, n_images, image_stride, shape)."""
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
-        raise ValueError(f"{name} must be a GPU tensor")
+    """(B, H, W) or (H, W) tensor -> (tensor, n_images, image_stride, shape).
+    The device is checked separately (_on_gpu), after the layout checks."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
     if t.dim() == 2:
         t3 = t.unsqueeze(0)
     elif t.dim() == 3:
@@ -370,40 +371,104 @@ def _batch_view(t: torch.Tensor, name: str):
     return t3, b, stride, abi.gc_shape(w, h, max(pitch, w))
 
 
+_OPS = {"dilate": abi.GC_DILATE, "erode": abi.GC_ERODE}
+
+
+def _op_code(op) -> int:
+    try:
+        return _OPS[op]
+    except (KeyError, TypeError):
+        raise ValueError(f"op is 'dilate' or 'erode', got {op!r}") from None
+
+
+def _check_batch_like(ref: torch.Tensor, t: torch.Tensor, names: str) -> None:
+    """t must have ref's shape, dtype, device and strides (the C ABI takes
+    one shape, pitch and image stride for both)."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{names}: expected a torch.Tensor")
+    if t.shape != ref.shape or t.dtype != ref.dtype or t.device != ref.device:
+        raise ValueError(f"{names}: shape, dtype and device must match "
+                         f"({tuple(t.shape)} {t.dtype} {t.device} vs {tuple(ref.shape)} {ref.dtype} {ref.device})")
+    # strides of dimensions of size 1 are never used to address memory
+    if t.numel() > 0 and any(n > 1 and a != b for n, a, b in zip(t.shape, t.stride(), ref.stride())):
+        raise ValueError(f"{names}: strides differ ({t.stride()} vs {ref.stride()})")
+
+
+def _check_codes(codes, n_images: int, n_steps: int, shape, device) -> None:
+    """codes: dense uint8 (n_images, n_steps, height, width) on device."""
+    if not isinstance(codes, torch.Tensor):
+        raise TypeError("codes must be a torch.Tensor")
+    want = (n_images, n_steps, shape.height, shape.width)
+    if codes.dtype != torch.uint8 or tuple(codes.shape) != want or codes.device != device:
+        raise ValueError(f"codes must be uint8 of shape {want} on {device} "
+                         f"(got {codes.dtype} {tuple(codes.shape)} on {codes.device})")
+    if not codes.is_contiguous():
+        raise ValueError("codes must be contiguous")
+
+
+def _on_gpu(t: torch.Tensor, name: str) -> None:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor (got {t.device})")
+
+
+def _check_float_images(*ts):
+    for name, t in ts:
+        if t.dtype not in (torch.float32, torch.float64):
+            raise TypeError(f"{name}: gradients need float32 or float64 images, got {t.dtype}")
+
+
 def geodesic_chain_fwd_codes(op, marker, mask, n_steps, out=None, codes=None):
     """n_steps geodesic steps that also record each pixel's source per step.
 
-    marker, mask: (H, W) or (B, H, W) float32/float64.  Returns (out, codes)
-    with codes of shape (B, n_steps, H, W) uint8 (B = 1 for 2-D inputs).
+    marker, mask: (H, W) or (B, H, W) float32/float64 with the same layout.
+    Returns (out, codes) with codes of shape (B, n_steps, H, W) uint8 (B = 1
+    for 2-D inputs).  A given out must have marker's layout; given codes
+    must be dense uint8 of that shape on the same device.
     """
-    m3, b, stride, shape = _batch_view(marker, "marker")
-    k3, b2, stride2, shape2 = _batch_view(mask, "mask")
-    if (b, shape.width, shape.height, shape.pitch, stride) != (b2, shape2.width, shape2.height, shape2.pitch,
-                                                               stride2) or marker.dtype != mask.dtype:
-        raise ValueError("marker and mask layouts differ")
+    opc = _op_code(op)
+    n_steps = int(n_steps)
+    _, b, stride, shape = _batch_view(marker, "marker")
+    _batch_view(mask, "mask")
+    _check_float_images(("marker", marker), ("mask", mask))
+    _check_batch_like(marker, mask, "marker/mask")
+    if out is not None:
+        _check_batch_like(marker, out, "marker/out")
+    if codes is not None:
+        _check_codes(codes, b, n_steps, shape, marker.device)
+    _on_gpu(marker, "marker")
     if out is None:
         out = torch.empty_strided(marker.shape, marker.stride(), dtype=marker.dtype, device=marker.device)
     if codes is None:
-        codes = torch.empty((b, int(n_steps), shape.height, shape.width), dtype=torch.uint8,
-                            device=marker.device)
+        codes = torch.empty((b, n_steps, shape.height, shape.width), dtype=torch.uint8, device=marker.device)
     with torch.cuda.device(marker.device):
-        st = abi.gc_geodesic_chain_fwd_codes(_dtype_code(marker), abi.GC_DILATE if op == "dilate" else abi.GC_ERODE,
-                                             _ptr(marker), _ptr(mask), _ptr(out), _ptr(codes), shape, b, stride,
-                                             int(n_steps), _stream(marker))
+        st = abi.gc_geodesic_chain_fwd_codes(_dtype_code(marker), opc, _ptr(marker), _ptr(mask), _ptr(out),
+                                             _ptr(codes), shape, b, stride, n_steps, _stream(marker))
     abi.check(st, "gc_geodesic_chain_fwd_codes")
     return out, codes
 
 
-def geodesic_chain_bwd(codes, grad_out, grad_mask, grad_marker=None):
-    """Reverse pass over codes (B, n, H, W): returns the gradient w.r.t. the
-    state before the first step; adds the mask's gradient into grad_mask."""
-    g3, b, stride, shape = _batch_view(grad_out, "grad_out")
-    n_steps = codes.shape[1]
+def geodesic_chain_bwd(op, codes, grad_out, grad_mask, grad_marker=None):
+    """Reverse pass over codes (B, n, H, W) recorded by
+    geodesic_chain_fwd_codes(op, ...): returns the gradient w.r.t. the state
+    before the first step and adds the mask's gradient into grad_mask.
+    grad_mask (and a given grad_marker) must have grad_out's layout."""
+    opc = _op_code(op)
+    _, b, stride, shape = _batch_view(grad_out, "grad_out")
+    _check_float_images(("grad_out", grad_out))
+    _check_batch_like(grad_out, grad_mask, "grad_out/grad_mask")
+    if not isinstance(codes, torch.Tensor) or codes.dim() != 4:
+        raise ValueError("codes must be a (B, n_steps, H, W) uint8 tensor")
+    n_steps = int(codes.shape[1])
+    _check_codes(codes, b, n_steps, shape, grad_out.device)
+    if grad_marker is not None:
+        _check_batch_like(grad_out, grad_marker, "grad_out/grad_marker")
+    _on_gpu(grad_out, "grad_out")
     if grad_marker is None:
         grad_marker = torch.empty_strided(grad_out.shape, grad_out.stride(), dtype=grad_out.dtype,
                                           device=grad_out.device)
     with torch.cuda.device(grad_out.device):
-        st = abi.gc_geodesic_chain_bwd(_dtype_code(grad_out), _ptr(codes), _ptr(grad_out), _ptr(grad_marker),
-                                       _ptr(grad_mask), shape, b, stride, int(n_steps), _stream(grad_out))
+        st = abi.gc_geodesic_chain_bwd(_dtype_code(grad_out), opc, _ptr(codes), _ptr(grad_out),
+                                       _ptr(grad_marker), _ptr(grad_mask), shape, b, stride, n_steps,
+                                       _stream(grad_out))
     abi.check(st, "gc_geodesic_chain_bwd")
     return grad_marker

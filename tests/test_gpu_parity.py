@@ -146,6 +146,24 @@ def test_in_place(n):
     assert_same(host(G), oracle.chain(oracle.ERODE, f, n), "plain in place")
 
 
+@pytest.mark.parametrize("n", [3, 4, 7])
+def test_in_place_one_step_per_launch(n):
+    """In place with one step per launch (forced by the tuning hook): an odd
+    number of launches first copies the marker into the work buffer and
+    then alternates, so no launch writes the buffer it reads."""
+    f, m = rand_pair((90, 150), np.uint8, seed=40 + n)
+    gc.set_tuning(1, -1)
+    try:
+        F, M = dev(f), dev(m)
+        gc.geodesic_dilate_chain(F, M, n, out=F)
+        assert_same(host(F), oracle.chain(oracle.DILATE, f, n, m), "geodesic in place, k = 1")
+        G = dev(f)
+        gc.erode_chain(G, n, out=G)
+        assert_same(host(G), oracle.chain(oracle.ERODE, f, n), "plain in place, k = 1")
+    finally:
+        gc.set_tuning(0, -1)
+
+
 def test_zero_steps_and_empty():
     f, m = rand_pair((50, 70), np.float32, seed=1)
     assert_same(gpu_chain(oracle.DILATE, f, m, 0), f, "n=0 copies the marker")
