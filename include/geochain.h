@@ -119,6 +119,34 @@ int gc_geodesic_erode_chain(gc_dtype dtype, const void *marker, const void *mask
                             void *hip_stream);
 
 /* ---------------------------------------------------------------------
+ * The geodesic chain for callers that cannot allocate device memory:
+ * code recorded into a HIP graph by stream capture, serving loops that
+ * must not allocate, harnesses that forbid hipMalloc.
+ *
+ * Computes what gc_geodesic_dilate_chain (op = GC_DILATE) or
+ * gc_geodesic_erode_chain (op = GC_ERODE) computes, with the same
+ * arguments, validation, aliasing rules and results, and calls no
+ * hipMalloc, hipFree or other allocating routine.  Its ping-pong image
+ * lives in a fixed array inside the library, one per device, held until
+ * the process ends:
+ *   - limit: the image's extent, ((height - 1) * pitch + width) elements,
+ *     must fit 16 MiB (16777216 bytes: a 4096 x 4096 u8 image, 2048 x 2048
+ *     f32, 1024 x 2048 f64); larger images return GC_ERR_UNSUPPORTED
+ *     before any HIP call;
+ *   - every call on one device shares that device's array: calls that
+ *     overlap in time on one device (two streams, or a graph replay beside
+ *     an eager call) race and give undefined results; the caller orders
+ *     them.  The array needs no clearing between calls (each launch writes
+ *     every pixel the next one reads);
+ *   - the first call on a device looks the array's address up
+ *     (hipGetSymbolAddress); make that first call outside stream capture.
+ * The measurement hook (gc_profile_*) does not record these calls.
+ * ------------------------------------------------------------------- */
+int gc_geodesic_chain_noalloc(gc_dtype dtype, gc_op op, const void *marker,
+                              const void *mask, void *out, gc_shape shape,
+                              int64_t n_steps, void *hip_stream);
+
+/* ---------------------------------------------------------------------
  * Plain chains (Eq. 1-2 iterated): n_steps 3x3 dilations (erosions),
  * equal to one (2 n_steps + 1)^2 window clipped to the image.
  * in may equal out.

@@ -19,6 +19,7 @@ from .ops import (  # noqa: F401
     geodesic_chain_fwd_codes,
     geodesic_dilate_chain,
     geodesic_erode_chain,
+    geodesic_chain_noalloc,
     granulometry,
     hfill,
     hmax,

@@ -744,6 +744,36 @@ static int run_chain(gc_dtype dtype, int op, int mode, const void *src, const vo
 }
 
 // ---------------------------------------------------------------------------
+// the chain entry point that allocates nothing
+// ---------------------------------------------------------------------------
+// Its ping-pong buffer: one array per device, held until the process ends.
+// In host code the name `scratch` stands for the symbol, not for device
+// memory; the device address comes from hipGetSymbolAddress, taken once per
+// device with that device current, and only that address is ever passed on.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)16 << 20;
+__device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+static int scratch_address(void **out) {
+    int dev = 0;
+    GC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(GC_ERR_UNSUPPORTED, "device ordinal %d beyond %d", dev, NOALLOC_MAX_DEVICES - 1);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        GC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(GC_ERR_HIP, "hipGetSymbolAddress returned a null address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GC_OK;
+}
+
+// ---------------------------------------------------------------------------
 // reconstruction
 // ---------------------------------------------------------------------------
 static int run_reconstruct(gc_dtype dtype, int op, const void *marker, const void *mask, void *out,
@@ -1912,6 +1942,28 @@ int gc_geodesic_erode_chain(gc_dtype dtype, const void *marker, const void *mask
                             gc_shape shape, int64_t n_steps, void *hip_stream) {
     GC_CHECK_DTYPE(dtype);
     return geodesic_chain(dtype, OP_ERODE, marker, mask, out, shape, n_steps, hip_stream);
+}
+
+int gc_geodesic_chain_noalloc(gc_dtype dtype, gc_op op, const void *marker, const void *mask, void *out,
+                              gc_shape shape, int64_t n_steps, void *hip_stream) {
+    GC_CHECK_DTYPE(dtype);
+    GC_CHECK_OP(op);
+    g_last_error.clear();
+    int rc = validate_images(dtype, marker, mask, out, shape);
+    if (rc != GC_OK) return rc;
+    if (!(shape.width == 0 || shape.height == 0) && !mask) return fail(GC_ERR_INVALID_ARG, "null mask");
+    if (n_steps < 0) return fail(GC_ERR_INVALID_ARG, "n_steps < 0");
+    if (shape.width == 0 || shape.height == 0) return GC_OK;
+    // the size check comes before any HIP call
+    const size_t bytes = (size_t)((shape.height - 1) * shape.pitch + shape.width) * elem_size(dtype);
+    if (bytes > NOALLOC_SCRATCH_BYTES)
+        return fail(GC_ERR_UNSUPPORTED, "image spans %zu bytes; the no-allocation chain holds at most %zu",
+                    bytes, NOALLOC_SCRATCH_BYTES);
+    void *work = nullptr;
+    rc = scratch_address(&work);
+    if (rc != GC_OK) return rc;
+    return run_chain(dtype, enum_bits(&op), MODE_GEODESIC, marker, mask, out, shape, n_steps, hip_stream, work,
+                     NOALLOC_SCRATCH_BYTES);
 }
 
 static int plain_chain(gc_dtype dtype, int op, const void *in, void *out, gc_shape shape,

@@ -86,6 +86,25 @@ def geodesic_erode_chain(marker, mask, n_steps, out=None):
     return _geodesic("gc_geodesic_erode_chain", marker, mask, n_steps, out)
 
 
+def geodesic_chain_noalloc(op, marker, mask, n_steps, out):
+    """The geodesic chain (Eq. 3-4) through the entry point that allocates
+    no device memory: its ping-pong image is the library's fixed per-device
+    array (images up to 16 MiB), shared by every such call on the device.
+    op is "dilate" or "erode"; out must be given (it may be marker)."""
+    _check_image(marker, "marker")
+    _check_image(mask, "mask")
+    _same_layout(marker, mask, "marker/mask")
+    if out is None:
+        raise ValueError("out must be given: this entry point is for callers that do not allocate")
+    _check_image(out, "out")
+    _same_layout(marker, out, "marker/out")
+    with torch.cuda.device(marker.device):
+        st = abi.gc_geodesic_chain_noalloc(_dtype_code(marker), _op_code(op), _ptr(marker), _ptr(mask),
+                                           _ptr(out), _shape(marker), int(n_steps), _stream(marker))
+    abi.check(st, "gc_geodesic_chain_noalloc")
+    return out
+
+
 def _plain(fn_name, x, n_steps, out):
     _check_image(x, "input")
     out = _out_like(x, out)

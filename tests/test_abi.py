@@ -199,3 +199,31 @@ def test_validate_values_validation():
     # nothing to scan: u8 holds no NaN or infinity, empty images hold nothing
     assert v(abi.GC_U8, FAKE, sh, 0, None) == abi.GC_OK
     assert v(abi.GC_F32, None, shape(0, 5, 0), 0, None) == abi.GC_OK
+
+
+def test_noalloc_chain_refusals():
+    """The chain that allocates nothing validates like the geodesic chains
+    and refuses images beyond its 16 MiB array before any HIP call."""
+    far = 1 << 30
+    # an unknown op, negative steps, a null mask
+    assert abi.gc_geodesic_chain_noalloc(abi.GC_U8, 5, FAKE, FAKE + far, FAKE + 2 * far,
+                                         shape(8, 8, 8), 1, None) == abi.GC_ERR_INVALID_ARG
+    assert abi.gc_geodesic_chain_noalloc(abi.GC_U8, abi.GC_DILATE, FAKE, FAKE + far, FAKE + 2 * far,
+                                         shape(8, 8, 8), -1, None) == abi.GC_ERR_INVALID_ARG
+    assert abi.gc_geodesic_chain_noalloc(abi.GC_U8, abi.GC_ERODE, FAKE, None, FAKE + 2 * far,
+                                         shape(8, 8, 8), 1, None) == abi.GC_ERR_INVALID_ARG
+    # out on the mask
+    assert abi.gc_geodesic_chain_noalloc(abi.GC_F32, abi.GC_DILATE, FAKE, FAKE + far, FAKE + far,
+                                         shape(8, 8, 8), 1, None) == abi.GC_ERR_ALIAS
+    # extents: 4096 x 4096 u8 is exactly 16 MiB; one more row, or f32 of the same
+    # shape, or a pitch that spreads the rows out, is too large
+    assert abi.gc_geodesic_chain_noalloc(abi.GC_U8, abi.GC_DILATE, FAKE, FAKE + far, FAKE + 2 * far,
+                                         shape(4096, 4097, 4096), 3, None) == abi.GC_ERR_UNSUPPORTED
+    assert "16777216" in abi.last_error()
+    assert abi.gc_geodesic_chain_noalloc(abi.GC_F32, abi.GC_ERODE, FAKE, FAKE + far, FAKE + 2 * far,
+                                         shape(2048, 2049, 2048), 3, None) == abi.GC_ERR_UNSUPPORTED
+    assert abi.gc_geodesic_chain_noalloc(abi.GC_F64, abi.GC_DILATE, FAKE, FAKE + far, FAKE + 2 * far,
+                                         shape(100, 2049, 1024), 3, None) == abi.GC_ERR_UNSUPPORTED
+    # empty images succeed without touching the device
+    assert abi.gc_geodesic_chain_noalloc(abi.GC_U8, abi.GC_DILATE, None, None, None,
+                                         shape(0, 5, 0), 3, None) == abi.GC_OK
