@@ -47,9 +47,9 @@
  *     validated before any HIP call; on error nothing is enqueued.
  *     gc_last_error() gives a detail message for the calling thread.
  *   - Calls that run concurrently on different streams are safe; each
- *     (device, stream) pair has its own workspace.  The exception is
- *     gc_plan_launch: two plans whose launches run at the same time on
- *     different streams are not supported (see the batch section).
+ *     (device, stream) pair has its own workspace (gc_plan objects have
+ *     their own), except gc_geodesic_chain_noalloc, whose calls on one
+ *     device share one buffer.
  *   - The chain entry points (geodesic and plain) may be recorded into a
  *     HIP graph by stream capture once a call of at least the same size has
  *     run on the capturing stream (that call sizes the stream's workspace;
@@ -286,13 +286,12 @@ int gc_quasi_distance(gc_dtype dtype, const void *f, int32_t *dist, void *residu
  *
  * gc_plan_launch replays the graph on hip_stream (asynchronous).  Launches
  * of one plan must not overlap each other (they share the workspace).
- * The kernel's workgroups wait for each other, so it needs all of its grid
- * resident on the device at once (the grid is sized to what the device
- * holds when nothing else runs): launches of two plans at the same time on
- * different streams, or beside long-running kernels of other work, are not
- * supported.  Such a launch does not hang: a wait that cannot finish gives
- * up after a bounded time and gc_plan_status reports GC_ERR_HIP (results
- * invalid).
+ * The kernel's workgroups draw work items in dependency order and wait
+ * only for items drawn before theirs, so a launch finishes whatever part of
+ * its grid is resident: plans may run at the same time on different
+ * streams, or beside other work.  Every wait is also bounded (2 seconds);
+ * past the bound the launch drains and gc_plan_status reports GC_ERR_HIP
+ * (results invalid).
  * With run-to-stability items it is synchronous instead: each replay runs
  * every active image for 4 blocks of 20 steps while the kernel records, per
  * block, which steps changed a pixel; between replays the host retires the

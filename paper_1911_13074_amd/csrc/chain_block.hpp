@@ -767,9 +767,10 @@ template <> struct PackedPick<OP_ERODE> {
 __device__ __forceinline__ uint32_t pack_rows(uint32_t lo, uint32_t hi) { return lo | (hi << 16) | PK_BIAS; }
 
 // Lanes per column group: 64 (one group) or 32 (two groups).
-template <int OP, int MODE, bool CLAMP, bool DETECT, int RPW, int NW, bool AGENT_STORES = false>
+template <int OP, int MODE, bool CLAMP, bool DETECT, int RPW, int NW, bool AGENT_STORES = false,
+          bool STAGED = false>
 __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int rx0, int ry0,
-                                                        uint32_t (*xch)[NW][2][128]) {
+                                                        uint32_t (*xch)[NW][2][128], uint8_t *stage) {
     static_assert(RPW % 2 == 0, "two rows per register");
     constexpr int H = RPW / 2;      // registers per column
     constexpr int CW = 2;
@@ -790,52 +791,132 @@ __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int 
     uint32_t m[CLAMP ? H : 1][CW];
 
     // ---- load region (rows j and j + H into register j) ----
-    const bool fast = rx0 >= 0 && ry0 >= 0 && rx0 + RX <= a.width && ry0 + RY <= a.height && (rx0 & 1) == 0 &&
-                      (a.pitch & 1) == 0 && pair_aligned(src) && (MODE != MODE_GEODESIC || pair_aligned(msk));
-    if (fast) {
-        const int64_t base = (int64_t)(ry0 + w * RPW) * a.pitch + rx0 + lane * 2;
-#pragma unroll
-        for (int j = 0; j < H; ++j) {
-            const uint32_t lo = *reinterpret_cast<const uint16_t *>(src + base + j * a.pitch);
-            const uint32_t hi = *reinterpret_cast<const uint16_t *>(src + base + (j + H) * a.pitch);
-            v[j][0] = pack_rows(lo & 0xFFu, hi & 0xFFu);
-            v[j][1] = pack_rows(lo >> 8, hi >> 8);
-            if constexpr (CLAMP) {
-                if constexpr (MODE == MODE_GEODESIC) {
-                    const uint32_t mlo = *reinterpret_cast<const uint16_t *>(msk + base + j * a.pitch);
-                    const uint32_t mhi = *reinterpret_cast<const uint16_t *>(msk + base + (j + H) * a.pitch);
+    // STAGED (per-launch kernel): through LDS, see below; otherwise (the
+    // persistent kernel, whose second workgroup per CU hides the loads) one
+    // two-byte access per lane, row pair and image.
+    // The store at the end follows the same choice.
+    bool fast = false;
+    if constexpr (STAGED) {
+        // Staged through LDS: the workgroup reads the region in 16-byte chunks of
+        // its rows, one wide load per chunk and image (at most two per thread),
+        // then each lane picks its two columns of its rows out of LDS.  Chunks
+        // outside the image are filled with the neutral value; a chunk that
+        // straddles the image border, or is not 16-byte aligned, is read byte by
+        // byte behind the inside-the-image test.
+        {
+            constexpr int CH = RX / 16;     // chunks per region row
+            constexpr int NCH = RY * CH;    // chunks per image
+            uint8_t *sv = stage;            // RY x RX state
+            uint8_t *sm = stage + RY * RX;  // RY x RX mask (clamped bodies)
+            const uint32_t bot4 = B::bottom() * 0x01010101u;
+            const uint32_t top4 = B::top() * 0x01010101u;
+            for (int i = threadIdx.x; i < NCH; i += 64 * NW) {
+                const int r = i / CH, c = i % CH;
+                const int y = ry0 + r, x = rx0 + 16 * c;
+                const bool yin = (unsigned)y < (unsigned)a.height;
+                const int64_t off = (int64_t)y * a.pitch + x;
+                uint4 cv = make_uint4(bot4, bot4, bot4, bot4);
+                uint4 cm = cv;
+                const bool whole = yin && x >= 0 && x + 16 <= a.width;
+                const bool none = !yin || x + 16 <= 0 || x >= a.width;
+                if (whole && ((uintptr_t)(src + off) & 15) == 0 &&
+                    (MODE != MODE_GEODESIC || ((uintptr_t)(msk + off) & 15) == 0)) {
+                    cv = *reinterpret_cast<const uint4 *>(src + off);
+                    if constexpr (CLAMP) {
+                        if constexpr (MODE == MODE_GEODESIC)
+                            cm = *reinterpret_cast<const uint4 *>(msk + off);
+                        else
+                            cm = make_uint4(top4, top4, top4, top4);
+                    }
+                } else if (!none) {
+                    uint32_t wv[4], wm[4];
+    #pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        wv[q] = 0;
+                        wm[q] = 0;
+    #pragma unroll
+                        for (int b = 0; b < 4; ++b) {
+                            const int xb = x + 4 * q + b;
+                            const bool in = yin && (unsigned)xb < (unsigned)a.width;
+                            const uint32_t pv = in ? (uint32_t)src[off + 4 * q + b] : B::bottom();
+                            uint32_t pm = B::bottom();
+                            if constexpr (MODE == MODE_GEODESIC)
+                                pm = in ? (uint32_t)msk[off + 4 * q + b] : B::bottom();
+                            else
+                                pm = in ? B::top() : B::bottom();
+                            wv[q] |= pv << (8 * b);
+                            wm[q] |= pm << (8 * b);
+                        }
+                    }
+                    cv = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+                    cm = make_uint4(wm[0], wm[1], wm[2], wm[3]);
+                }
+                *reinterpret_cast<uint4 *>(sv + r * RX + 16 * c) = cv;
+                if constexpr (CLAMP) *reinterpret_cast<uint4 *>(sm + r * RX + 16 * c) = cm;
+            }
+            __syncthreads();
+            const int base = (w * RPW) * RX + lane * 2;
+    #pragma unroll
+            for (int j = 0; j < H; ++j) {
+                const uint32_t lo = *reinterpret_cast<const uint16_t *>(sv + base + j * RX);
+                const uint32_t hi = *reinterpret_cast<const uint16_t *>(sv + base + (j + H) * RX);
+                v[j][0] = pack_rows(lo & 0xFFu, hi & 0xFFu);
+                v[j][1] = pack_rows(lo >> 8, hi >> 8);
+                if constexpr (CLAMP) {
+                    const uint32_t mlo = *reinterpret_cast<const uint16_t *>(sm + base + j * RX);
+                    const uint32_t mhi = *reinterpret_cast<const uint16_t *>(sm + base + (j + H) * RX);
                     m[j][0] = pack_rows(mlo & 0xFFu, mhi & 0xFFu);
                     m[j][1] = pack_rows(mlo >> 8, mhi >> 8);
-                } else {
-                    m[j][0] = m[j][1] = pack_rows(B::top(), B::top());
                 }
             }
         }
     } else {
-#pragma unroll
-        for (int j = 0; j < H; ++j) {
-#pragma unroll
-            for (int c = 0; c < CW; ++c) {
-                const int x = rx0 + lane * CW + c;
-                const bool xin = (unsigned)x < (unsigned)a.width;
-                uint32_t vv[2], mm[2];
-#pragma unroll
-                for (int half = 0; half < 2; ++half) {
-                    const int y = ry0 + w * RPW + j + half * H;
-                    const bool in = xin && (unsigned)y < (unsigned)a.height;
-                    const int64_t off = (int64_t)y * a.pitch + x;
-                    vv[half] = in ? (uint32_t)src[off] : B::bottom();
-                    if constexpr (MODE == MODE_GEODESIC)
-                        mm[half] = in ? (uint32_t)msk[off] : B::bottom();
-                    else
-                        mm[half] = in ? B::top() : B::bottom();
+        fast = rx0 >= 0 && ry0 >= 0 && rx0 + RX <= a.width && ry0 + RY <= a.height && (rx0 & 1) == 0 &&
+                          (a.pitch & 1) == 0 && pair_aligned(src) && (MODE != MODE_GEODESIC || pair_aligned(msk));
+        if (fast) {
+            const int64_t base = (int64_t)(ry0 + w * RPW) * a.pitch + rx0 + lane * 2;
+    #pragma unroll
+            for (int j = 0; j < H; ++j) {
+                const uint32_t lo = *reinterpret_cast<const uint16_t *>(src + base + j * a.pitch);
+                const uint32_t hi = *reinterpret_cast<const uint16_t *>(src + base + (j + H) * a.pitch);
+                v[j][0] = pack_rows(lo & 0xFFu, hi & 0xFFu);
+                v[j][1] = pack_rows(lo >> 8, hi >> 8);
+                if constexpr (CLAMP) {
+                    if constexpr (MODE == MODE_GEODESIC) {
+                        const uint32_t mlo = *reinterpret_cast<const uint16_t *>(msk + base + j * a.pitch);
+                        const uint32_t mhi = *reinterpret_cast<const uint16_t *>(msk + base + (j + H) * a.pitch);
+                        m[j][0] = pack_rows(mlo & 0xFFu, mhi & 0xFFu);
+                        m[j][1] = pack_rows(mlo >> 8, mhi >> 8);
+                    } else {
+                        m[j][0] = m[j][1] = pack_rows(B::top(), B::top());
+                    }
                 }
-                v[j][c] = pack_rows(vv[0], vv[1]);
-                if constexpr (CLAMP) m[j][c] = pack_rows(mm[0], mm[1]);
+            }
+        } else {
+    #pragma unroll
+            for (int j = 0; j < H; ++j) {
+    #pragma unroll
+                for (int c = 0; c < CW; ++c) {
+                    const int x = rx0 + lane * CW + c;
+                    const bool xin = (unsigned)x < (unsigned)a.width;
+                    uint32_t vv[2], mm[2];
+    #pragma unroll
+                    for (int half = 0; half < 2; ++half) {
+                        const int y = ry0 + w * RPW + j + half * H;
+                        const bool in = xin && (unsigned)y < (unsigned)a.height;
+                        const int64_t off = (int64_t)y * a.pitch + x;
+                        vv[half] = in ? (uint32_t)src[off] : B::bottom();
+                        if constexpr (MODE == MODE_GEODESIC)
+                            mm[half] = in ? (uint32_t)msk[off] : B::bottom();
+                        else
+                            mm[half] = in ? B::top() : B::bottom();
+                    }
+                    v[j][c] = pack_rows(vv[0], vv[1]);
+                    if constexpr (CLAMP) m[j][c] = pack_rows(mm[0], mm[1]);
+                }
             }
         }
     }
-
     // Change detection: per register, the bits of its core pixels (16-bit
     // halves of core rows, in columns of the core).  A step changed the core
     // iff some (new ^ old) & mask is nonzero; the encodings are unique, so
@@ -1000,36 +1081,101 @@ __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int 
         run_steps(std::false_type{});
     for (int s = busy; s < k; ++s) __syncthreads();
 
-    // ---- store the core ----
-#pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-        const int ry = w * RPW + r;
-        const int y = ry0 + ry;
-        const bool yok = ry >= halo && ry < halo + a.core_y && y < a.height;
-        if (!yok) continue;
-        const int j = r < H ? r : r - H;
-        const int sh = r < H ? 0 : 16;
-        const uint32_t c0 = (v[j][0] >> sh) & 0xFFu, c1 = (v[j][1] >> sh) & 0xFFu;
-        const int cx = lane * 2;
-        const int x = rx0 + cx;
-        uint8_t *p = dst + (int64_t)y * a.pitch + x;
-        const bool in0 = cx >= halo && cx < halo + a.core_x && x < a.width;
-        const bool in1 = cx + 1 >= halo && cx + 1 < halo + a.core_x && x + 1 < a.width;
-        if constexpr (AGENT_STORES) {
-            // coherent at agent scope on their own, so the release that
-            // publishes the tile finds (almost) nothing to write back
-            if (in0 && in1 && (fast || pair_aligned(p))) {
-                __hip_atomic_store(reinterpret_cast<uint16_t *>(p), (uint16_t)(c0 | (c1 << 8)), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                if (in0) __hip_atomic_store(p, (uint8_t)c0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (in1) __hip_atomic_store(p + 1, (uint8_t)c1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if constexpr (STAGED) {
+        // ---- store the core ----
+        // Staged through LDS as well: every lane puts its pixel pairs back into
+        // its rows of the staging buffer, then the workgroup writes the core row
+        // by row in the widest chunks (16, 8, 4, 2 or 1 bytes) that the core's
+        // row starts, its width and the pitch allow, instead of one two-byte
+        // store per lane and row.
+        {
+            uint8_t *sv = stage;
+    #pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                const int j = r < H ? r : r - H;
+                const int sh = r < H ? 0 : 16;
+                const uint32_t c0 = (v[j][0] >> sh) & 0xFFu, c1 = (v[j][1] >> sh) & 0xFFu;
+                *reinterpret_cast<uint16_t *>(sv + (w * RPW + r) * RX + lane * 2) = (uint16_t)(c0 | (c1 << 8));
             }
-        } else if (in0 && in1 && (fast || pair_aligned(p))) {
-            *reinterpret_cast<uint16_t *>(p) = (uint16_t)(c0 | (c1 << 8));
-        } else {
-            if (in0) *p = (uint8_t)c0;
-            if (in1) p[1] = (uint8_t)c1;
+            __syncthreads();
+            // the core inside the image, in region coordinates
+            const int cx0 = halo, cx1 = min(halo + a.core_x, a.width - rx0);
+            const int cy0 = halo, cy1 = min(halo + a.core_y, a.height - ry0);
+            if (cx1 > cx0 && cy1 > cy0) {
+                const int len = cx1 - cx0;
+                uint8_t *row0 = dst + (int64_t)(ry0 + cy0) * a.pitch + rx0 + cx0;
+                const uintptr_t al = (uintptr_t)row0 | (uintptr_t)a.pitch | (uintptr_t)len | (uintptr_t)cx0;
+                // agent-scope stores go out as at most 8-byte atomics
+                int G = AGENT_STORES ? 8 : 16;
+                while (al & (uintptr_t)(G - 1)) G >>= 1;
+                G = __builtin_amdgcn_readfirstlane(G);
+                const int per_row = len / G;
+                const int n = (cy1 - cy0) * per_row;
+                for (int i = threadIdx.x; i < n; i += 64 * NW) {
+                    const int r = i / per_row, c = i - r * per_row;
+                    const uint8_t *sp = sv + (cy0 + r) * RX + cx0 + c * G;
+                    uint8_t *dp = row0 + (int64_t)r * a.pitch + c * G;
+                    if constexpr (AGENT_STORES) {
+                        // coherent at agent scope on their own, so the release that
+                        // publishes the tile finds (almost) nothing to write back
+                        if (G == 8)
+                            __hip_atomic_store(reinterpret_cast<uint64_t *>(dp), *reinterpret_cast<const uint64_t *>(sp),
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        else if (G == 4)
+                            __hip_atomic_store(reinterpret_cast<uint32_t *>(dp), *reinterpret_cast<const uint32_t *>(sp),
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        else if (G == 2)
+                            __hip_atomic_store(reinterpret_cast<uint16_t *>(dp), *reinterpret_cast<const uint16_t *>(sp),
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        else
+                            __hip_atomic_store(dp, *sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    } else {
+                        if (G == 16)
+                            *reinterpret_cast<uint4 *>(dp) = *reinterpret_cast<const uint4 *>(sp);
+                        else if (G == 8)
+                            *reinterpret_cast<uint2 *>(dp) = *reinterpret_cast<const uint2 *>(sp);
+                        else if (G == 4)
+                            *reinterpret_cast<uint32_t *>(dp) = *reinterpret_cast<const uint32_t *>(sp);
+                        else if (G == 2)
+                            *reinterpret_cast<uint16_t *>(dp) = *reinterpret_cast<const uint16_t *>(sp);
+                        else
+                            *dp = *sp;
+                    }
+                }
+            }
+        }
+    } else {
+        // ---- store the core ----
+    #pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const int ry = w * RPW + r;
+            const int y = ry0 + ry;
+            const bool yok = ry >= halo && ry < halo + a.core_y && y < a.height;
+            if (!yok) continue;
+            const int j = r < H ? r : r - H;
+            const int sh = r < H ? 0 : 16;
+            const uint32_t c0 = (v[j][0] >> sh) & 0xFFu, c1 = (v[j][1] >> sh) & 0xFFu;
+            const int cx = lane * 2;
+            const int x = rx0 + cx;
+            uint8_t *p = dst + (int64_t)y * a.pitch + x;
+            const bool in0 = cx >= halo && cx < halo + a.core_x && x < a.width;
+            const bool in1 = cx + 1 >= halo && cx + 1 < halo + a.core_x && x + 1 < a.width;
+            if constexpr (AGENT_STORES) {
+                // coherent at agent scope on their own, so the release that
+                // publishes the tile finds (almost) nothing to write back
+                if (in0 && in1 && (fast || pair_aligned(p))) {
+                    __hip_atomic_store(reinterpret_cast<uint16_t *>(p), (uint16_t)(c0 | (c1 << 8)), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    if (in0) __hip_atomic_store(p, (uint8_t)c0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (in1) __hip_atomic_store(p + 1, (uint8_t)c1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            } else if (in0 && in1 && (fast || pair_aligned(p))) {
+                *reinterpret_cast<uint16_t *>(p) = (uint16_t)(c0 | (c1 << 8));
+            } else {
+                if (in0) *p = (uint8_t)c0;
+                if (in1) p[1] = (uint8_t)c1;
+            }
         }
     }
     return step_bits;
@@ -1037,13 +1183,24 @@ __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int 
 
 template <int G> constexpr int lanes_per_group() { return 64 / G; }
 
+// LDS bytes of the region staging buffer: state and mask of the packed u8
+// body when it stages its loads and stores (STAGED); a token size otherwise.
+template <typename T, int CW, int RPW, int NW, int G, bool STAGED>
+constexpr int stage_bytes() {
+    return (STAGED && std::is_same<T, uint8_t>::value && G == 1 && CW == 2 && RPW % 2 == 0)
+               ? 2 * (64 * CW) * (NW * RPW)
+               : 16;
+}
+
 // Plain chains skip the border fence for regions entirely inside the image.
 // AGENT_STORES: the core is written with agent-scope stores (packed and
 // generic bodies; the persistent kernel, which publishes tiles to other
 // workgroups).
-template <typename T, int OP, int MODE, bool DETECT, int CW, int RPW, int NW, int G = 1, bool AGENT_STORES = false>
+template <typename T, int OP, int MODE, bool DETECT, int CW, int RPW, int NW, int G = 1, bool AGENT_STORES = false,
+          bool STAGED = false>
 __device__ __forceinline__ uint32_t chain_block_dispatch(
-    const BlockArgs &a, int rx0, int ry0, typename RegOf<T>::type (*xch)[NW][2 * G][lanes_per_group<G>() * CW]) {
+    const BlockArgs &a, int rx0, int ry0, typename RegOf<T>::type (*xch)[NW][2 * G][lanes_per_group<G>() * CW],
+    uint8_t *stage) {
     constexpr int RX = lanes_per_group<G>() * CW;
     constexpr int RY = NW * RPW * G;
     if constexpr (G == 2) {
@@ -1058,10 +1215,10 @@ __device__ __forceinline__ uint32_t chain_block_dispatch(
         // u8: two rows per register, packed half-precision extrema on encoded pixels
         if constexpr (MODE == MODE_PLAIN) {
             const bool inside = rx0 >= 0 && ry0 >= 0 && rx0 + RX <= a.width && ry0 + RY <= a.height;
-            if (inside) return chain_block_body_pk<OP, MODE, false, DETECT, RPW, NW, AGENT_STORES>(a, rx0, ry0, xch);
-            return chain_block_body_pk<OP, MODE, true, DETECT, RPW, NW, AGENT_STORES>(a, rx0, ry0, xch);
+            if (inside) return chain_block_body_pk<OP, MODE, false, DETECT, RPW, NW, AGENT_STORES, STAGED>(a, rx0, ry0, xch, stage);
+            return chain_block_body_pk<OP, MODE, true, DETECT, RPW, NW, AGENT_STORES, STAGED>(a, rx0, ry0, xch, stage);
         } else {
-            return chain_block_body_pk<OP, MODE, true, DETECT, RPW, NW, AGENT_STORES>(a, rx0, ry0, xch);
+            return chain_block_body_pk<OP, MODE, true, DETECT, RPW, NW, AGENT_STORES, STAGED>(a, rx0, ry0, xch, stage);
         }
     } else if constexpr (MODE == MODE_PLAIN) {
         const bool inside = rx0 >= 0 && ry0 >= 0 && rx0 + RX <= a.width && ry0 + RY <= a.height;
@@ -1098,7 +1255,9 @@ __global__ __launch_bounds__(64 * NW) void chain_block_kernel(BlockArgs a) {
     const int ry0 = ty * a.core_y - a.halo;
     using R = typename RegOf<T>::type;
     __shared__ __attribute__((aligned(16))) R xch[2][NW][2 * G][lanes_per_group<G>() * CW];
-    const uint32_t bits = chain_block_dispatch<T, OP, MODE, DETECT, CW, RPW, NW, G>(a, rx0, ry0, xch);
+    __shared__ __attribute__((aligned(16))) uint8_t stage[stage_bytes<T, CW, RPW, NW, G, true>()];
+    const uint32_t bits =
+        chain_block_dispatch<T, OP, MODE, DETECT, CW, RPW, NW, G, false, true>(a, rx0, ry0, xch, stage);
     if constexpr (DETECT) {
         if (bits != 0 && (threadIdx.x & 63) == 0) atomicOr(a.change_word, bits);
     }

@@ -339,3 +339,48 @@ def test_plan_relaunch_and_refusals():
         plan.close()
     with pytest.raises(gc.GeochainError):
         gc.BatchPlan("dilate", [(F, None, -1)])
+
+
+@pytest.fixture
+def plan_grid(monkeypatch):
+    """Sets the grid of plans built inside the test (GEOCHAIN_PLAN_GRID)."""
+    def set_grid(n):
+        monkeypatch.setenv("GEOCHAIN_PLAN_GRID", str(n))
+    yield set_grid
+    monkeypatch.delenv("GEOCHAIN_PLAN_GRID", raising=False)
+
+
+@pytest.mark.parametrize("grid", [1, 3, 4096])
+def test_any_grid_finishes(plan_grid, grid):
+    """Items are drawn in list order, so the launch finishes whatever part
+    of its grid is resident: one workgroup doing everything, three, or 4096
+    workgroups (eight times what fits on the device at once, so most of them
+    start only after others have left)."""
+    plan_grid(grid)
+    items = make_batch(np.uint8, seed=40 + grid, count=7, lo=60, hi=420, n_lo=15, n_hi=140)
+    plan = gc.BatchPlan("dilate", [(dev(f), dev(m), n) for f, m, n in items])
+    assert plan.info()["workgroups"] == grid
+    plan.launch()
+    plan.status()
+    check_items("dilate", items, plan.outs)
+
+
+def test_two_plans_at_the_same_time():
+    """Two plans, each with a grid of all the workgroups the device holds,
+    replayed at the same time on two streams: they compete for the CUs, and
+    both finish with exact results."""
+    a_items = make_batch(np.uint8, seed=51, count=9, lo=100, hi=700, n_lo=40, n_hi=300)
+    b_items = make_batch(np.float32, seed=52, count=6, lo=100, hi=500, n_lo=30, n_hi=200)
+    plan_a = gc.BatchPlan("dilate", [(dev(f), dev(m), n) for f, m, n in a_items])
+    plan_b = gc.BatchPlan("erode", [(dev(f), dev(m), n) for f, m, n in b_items])
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for _ in range(2):
+        with torch.cuda.stream(s1):
+            plan_a.launch()
+        with torch.cuda.stream(s2):
+            plan_b.launch()
+    plan_a.status()
+    plan_b.status()
+    check_items("dilate", a_items, plan_a.outs)
+    check_items("erode", b_items, plan_b.outs)
