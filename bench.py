@@ -475,17 +475,21 @@ def main():
         fd, md, gd = workloads.differentiable_f32(size=S)
         Fd, Md, Gd = (torch.from_numpy(a).to(dev) for a in (fd, md, gd))
 
-        def fwd_bwd():
+        def fwd_bwd(method="sources"):
             Fr = Fd.detach().requires_grad_(True)
             Mr = Md.detach().requires_grad_(True)
-            gc.geodesic_chain(Fr, Mr, 200, op="dilate", checkpoint_every=32).backward(Gd)
+            gc.geodesic_chain(Fr, Mr, 200, op="dilate", checkpoint_every=32, method=method).backward(Gd)
 
         def fwd_only():
             with torch.no_grad():
                 gc.geodesic_chain(Fd, Md, 200, op="dilate", checkpoint_every=32)
 
         px_d = Fd.numel() * 200
+        # Two ways through the same gradient: source ids (the per-step
+        # routes composed over each 32-step segment, one scatter per
+        # segment; the default) and per-step codes with the reverse gather.
         ms_fb = timed(fwd_bwd, 3, 1)
+        ms_fb_codes = timed(lambda: fwd_bwd("codes"), 3, 1)
         ms_fo = timed(fwd_only, 3, 1)
         # The two gradient kernels run up to 8 steps per launch on tiles held
         # in LDS.  Algorithmic HBM bytes per pixel and launch of k steps, s =
@@ -496,20 +500,43 @@ def main():
         gm = torch.zeros_like(Md)
         c_ms, c_n, c_st = kernel_profile(lambda: gc.geodesic_chain_fwd_codes("dilate", Fd, Md, 32, codes=codes), 2)
         b_ms, b_n, b_st = kernel_profile(lambda: gc.geodesic_chain_bwd("dilate", codes, Gd, gm), 2)
+        del codes
+        # Source ids: the recomputation of one 32-step segment carrying ids
+        # (read state, mask and ids, write state and ids: 5s per pixel and
+        # launch of up to 8 steps; the first launch reads no ids), and the
+        # scatter (read ids and gradient, read-modify-write one leaf
+        # gradient per pixel, zero the marker gradient first: about 5s).
+        _, srcs = gc.geodesic_chain_fwd_sources("dilate", Fd, Md, 32)
+        s_ms, s_n, s_st = kernel_profile(lambda: gc.geodesic_chain_fwd_sources("dilate", Fd, Md, 32, sources=srcs), 2)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        gc.geodesic_chain_bwd_sources(srcs, Gd, gm)
+        t0.record()
+        for _ in range(4):
+            gc.geodesic_chain_bwd_sources(srcs, Gd, gm)
+        t1.record()
+        t1.synchronize()
+        sc_ms = t0.elapsed_time(t1) / 4
         npx = Fd.numel()
-        k_c, k_b = c_st / max(c_n, 1), b_st / max(b_n, 1)
+        k_c, k_b, k_s = c_st / max(c_n, 1), b_st / max(b_n, 1), s_st / max(s_n, 1)
         extra["fwd_bwd_16x1024_f32_200"] = {
-            "gpx_steps_per_s": round(px_d / ms_fb / 1e6, 2), "ms": round(ms_fb, 3),
+            "gpx_steps_per_s": round(px_d / ms_fb / 1e6, 2), "ms": round(ms_fb, 3), "method": "sources",
             "forward_only_gpx_steps_per_s": round(px_d / ms_fo / 1e6, 2),
             "vs_plain": round(px_d / ms_fb / 1e6 / value, 4),
             "vs_f32_forward": round(ms_fo / ms_fb, 4), "checkpoint_every": 32,
+            "codes_method": {"gpx_steps_per_s": round(px_d / ms_fb_codes / 1e6, 2), "ms": round(ms_fb_codes, 3)},
+            "sources_kernel": {"avg_launch_ms": round(s_ms, 4), "steps_per_launch": round(k_s, 2),
+                               "gpx_steps_per_s": round(npx * k_s / (s_ms * 1e-3) / 1e9, 1),
+                               "hbm_gb_s": round(20 * npx / (s_ms * 1e-3) / 1e9, 1), "peak_gb_s": 8000},
+            "scatter": {"ms_per_segment": round(sc_ms, 4),
+                        "hbm_gb_s": round(20 * npx / (sc_ms * 1e-3) / 1e9, 1), "peak_gb_s": 8000},
             "codes_kernel": {"avg_launch_ms": round(c_ms, 4), "steps_per_launch": round(k_c, 2),
                              "gpx_steps_per_s": round(npx * k_c / (c_ms * 1e-3) / 1e9, 1),
                              "hbm_gb_s": round((12 + k_c) * npx / (c_ms * 1e-3) / 1e9, 1), "peak_gb_s": 8000},
             "bwd_kernel": {"avg_launch_ms": round(b_ms, 4), "steps_per_launch": round(k_b, 2),
                            "gpx_steps_per_s": round(npx * k_b / (b_ms * 1e-3) / 1e9, 1),
                            "hbm_gb_s": round((16 + k_b) * npx / (b_ms * 1e-3) / 1e9, 1), "peak_gb_s": 8000}}
-        del codes, gm
+        del srcs, gm
         del Fd, Md, Gd
         for dt_name, dt in (("u8", np.uint8), ("f32", np.float32), ("f64", np.float64)):
             x = torch.from_numpy(workloads.plain_input(dt, size=S)).to(dev)

@@ -394,6 +394,45 @@ int gc_geodesic_chain_bwd(gc_dtype dtype, gc_op op, const uint8_t *codes, const 
                           int64_t image_stride, int64_t n_steps, void *hip_stream);
 
 /* ---------------------------------------------------------------------
+ * The same gradient through source ids (not in the paper): the per-step
+ * routes above, composed over a run of steps.
+ *
+ * Following the codes of a pixel p of the final state backward through the
+ * steps ends at a pixel of the state before step 0, or at the mask value of
+ * some pixel (where the mask won a clamp): p's source, of which p's value
+ * is a copy.  The gradient of sum(grad_out * out) w.r.t. marker pixel r is
+ * the sum of grad_out(p) over the p whose source is marker pixel r, and
+ * likewise for mask pixels; these are the sums gc_geodesic_chain_bwd forms
+ * step by step, added in another order.
+ *
+ * gc_geodesic_chain_fwd_sources runs n_steps geodesic steps (out as in
+ * gc_geodesic_{dilate,erode}_chain, n_steps = 0 copies) and writes, for
+ * every pixel of out, its source id: the element offset y * pitch + x of the
+ * source pixel within its image, with the top bit (0x80000000) set if the
+ * source is the mask.  The choices are those of the codes (first extremal
+ * neighbour in raster order, the mask winning ties).  sources:
+ * caller-owned device buffer of uint32 with the images' layout (pitch and
+ * image_stride in elements, as for the images).  Images may span at most
+ * 2^31 - 1 elements each ((height - 1) * pitch + width), else
+ * GC_ERR_UNSUPPORTED.  sources must not overlap the images.
+ *
+ * gc_geodesic_chain_bwd_sources WRITES grad_marker (zero, then every
+ * pixel's grad_out added to the marker pixel its id names) and ADDS into
+ * grad_mask (grad_out of the pixels whose source is a mask pixel, to that
+ * pixel).  The additions into one pixel happen in an unspecified order
+ * (hardware atomics), so results can differ between calls in the last
+ * bits of the sums.  grad_marker, grad_mask, grad_out and sources must not
+ * overlap.  Batches as above (one launch per 8 steps, and two launches for
+ * the reverse pass).
+ * ------------------------------------------------------------------- */
+int gc_geodesic_chain_fwd_sources(gc_dtype dtype, gc_op op, const void *marker, const void *mask,
+                                  void *out, uint32_t *sources, gc_shape shape, int32_t n_images,
+                                  int64_t image_stride, int64_t n_steps, void *hip_stream);
+int gc_geodesic_chain_bwd_sources(gc_dtype dtype, const uint32_t *sources, const void *grad_out,
+                                  void *grad_marker, void *grad_mask, gc_shape shape, int32_t n_images,
+                                  int64_t image_stride, void *hip_stream);
+
+/* ---------------------------------------------------------------------
  * Tuning hook: override the temporal-block depth (steps fused per launch)
  * and the tile family used by the chain kernels.  block_steps = 0 and
  * tile = -1 restore the built-in choice.  Process-wide; intended for the

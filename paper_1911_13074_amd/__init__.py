@@ -16,6 +16,8 @@ from .ops import (  # noqa: F401
     dome,
     erode_chain,
     geodesic_chain_bwd,
+    geodesic_chain_bwd_sources,
+    geodesic_chain_fwd_sources,
     geodesic_chain_fwd_codes,
     geodesic_dilate_chain,
     geodesic_erode_chain,

@@ -84,6 +84,8 @@ SIGNATURES = {
     "gc_geodesic_chain_fwd_codes": (ctypes.c_int, [_DT, _DT, _VP, _VP, _VP, _VP, gc_shape, _I32, _I64,
                                                    _I64, _VP]),
     "gc_geodesic_chain_bwd": (ctypes.c_int, [_DT, _DT, _VP, _VP, _VP, _VP, gc_shape, _I32, _I64, _I64, _VP]),
+    "gc_geodesic_chain_fwd_sources": (ctypes.c_int, [_DT, _DT, _VP, _VP, _VP, _VP, gc_shape, _I32, _I64, _I64, _VP]),
+    "gc_geodesic_chain_bwd_sources": (ctypes.c_int, [_DT, _VP, _VP, _VP, _VP, gc_shape, _I32, _I64, _VP]),
     "gc_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "gc_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), _P_I64, _P_I64]),
 }

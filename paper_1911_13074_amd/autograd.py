@@ -2,9 +2,18 @@
 
 GeodesicChainFunction: forward runs the chain with the fast kernels and
 keeps the state every `checkpoint_every` steps; backward walks the segments
-from last to first, recomputes each one from its checkpoint with the
-code-recording kernel and runs the reverse gather over it.  Memory: one
-image per checkpoint plus one byte per pixel-step of a single segment.
+from last to first and recomputes each one from its checkpoint, then takes
+the gradient through it in one of two ways:
+  method="sources": the recomputation carries each pixel's source id (the
+      per-step routes composed over the segment), and one scatter moves
+      the segment's upstream gradient onto the marker and mask pixels;
+      memory: one image per checkpoint plus one 32-bit id per pixel;
+  method="codes": the recomputation records a code per pixel and step, and
+      the reverse gather walks the steps back one by one; memory: one image
+      per checkpoint plus one byte per pixel-step of a single segment.
+Both give the same gradient: the same contributions, summed in another
+order (float64 "codes" results equal the oracle's step-by-step scatter bit
+for bit; "sources" adds with hardware atomics in no fixed order).
 """
 import torch
 
@@ -13,7 +22,9 @@ from . import ops
 
 class GeodesicChainFunction(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, marker, mask, n_steps, op, checkpoint_every):
+    def forward(ctx, marker, mask, n_steps, op, checkpoint_every, method):
+        if method not in ("sources", "codes"):
+            raise ValueError("method is 'sources' or 'codes'")
         if marker.dtype not in (torch.float32, torch.float64):
             raise TypeError("gradients need float32 or float64 images")
         n_steps = int(n_steps)
@@ -36,7 +47,7 @@ class GeodesicChainFunction(torch.autograd.Function):
                 ckpts.append(cur.view_as(marker))
         # the last segment's state is a fresh tensor that no checkpoint holds
         out = cur.view_as(marker) if n_steps > 0 else marker.clone()
-        ctx.n_steps, ctx.seg, ctx.op = n_steps, seg, op
+        ctx.n_steps, ctx.seg, ctx.op, ctx.method = n_steps, seg, op, method
         ctx.save_for_backward(mask, *ckpts)
         return out
 
@@ -48,13 +59,20 @@ class GeodesicChainFunction(torch.autograd.Function):
         starts = list(range(0, ctx.n_steps, ctx.seg))
         for i in reversed(range(len(starts))):
             n = min(ctx.seg, ctx.n_steps - starts[i])
-            _, codes = ops.geodesic_chain_fwd_codes(ctx.op, ckpts[i], mask, n)
-            g = ops.geodesic_chain_bwd(ctx.op, codes, g, gm)
-            del codes
-        return g, gm, None, None, None
+            if ctx.method == "sources":
+                _, src = ops.geodesic_chain_fwd_sources(ctx.op, ckpts[i], mask, n)
+                g = ops.geodesic_chain_bwd_sources(src, g, gm)
+                del src
+            else:
+                _, codes = ops.geodesic_chain_fwd_codes(ctx.op, ckpts[i], mask, n)
+                g = ops.geodesic_chain_bwd(ctx.op, codes, g, gm)
+                del codes
+        return g, gm, None, None, None, None
 
 
-def geodesic_chain(marker, mask, n_steps, op="dilate", checkpoint_every=32):
+def geodesic_chain(marker, mask, n_steps, op="dilate", checkpoint_every=32, method="sources"):
     """Differentiable n_steps geodesic dilations ('dilate') or erosions
-    ('erode') of marker under mask; (H, W) or (B, H, W) float tensors."""
-    return GeodesicChainFunction.apply(marker, mask, n_steps, op, checkpoint_every)
+    ('erode') of marker under mask; (H, W) or (B, H, W) float tensors.
+    method: 'sources' (composed routes, one scatter per segment) or 'codes'
+    (per-step codes and reverse gather)."""
+    return GeodesicChainFunction.apply(marker, mask, n_steps, op, checkpoint_every, method)

@@ -1862,6 +1862,97 @@ static int run_bwd(gc_dtype dtype, const uint8_t *codes, const void *g_out, void
     return GC_OK;
 }
 
+// Forward with source ids: blocks of up to GB_K steps per launch; values
+// ping-pong through the workspace as in run_fwd_codes, ids likewise through
+// two id planes, the last block writing out and sources.
+template <typename T>
+static void launch_src(int op, const SrcBlockArgs &a, const gc_shape &s, int32_t n, hipStream_t st) {
+    const dim3 grid = block_grid<T>(s, n), block(GradTile<T>::THREADS);
+    if (op == OP_DILATE)
+        hipLaunchKernelGGL((block_src_kernel<T, OP_DILATE>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((block_src_kernel<T, OP_ERODE>), grid, block, 0, st, a);
+}
+
+static int run_fwd_sources(gc_dtype dtype, int op, const void *marker, const void *mask, void *out,
+                           uint32_t *sources, const gc_shape &s, int32_t n, int64_t stride, int64_t n_steps,
+                           hipStream_t st) {
+    const size_t es = elem_size(dtype);
+    if (s.width == 0 || s.height == 0 || n == 0) return GC_OK;
+    const int64_t span = (s.height - 1) * s.pitch + s.width;
+    const int64_t istride = n > 1 ? stride : span;
+    const int64_t batch_elems = (int64_t)(n - 1) * istride + span;
+    const size_t half = ((size_t)batch_elems * es + 255) & ~size_t(255);
+    const size_t ihalf = ((size_t)batch_elems * 4 + 255) & ~size_t(255);
+    const int64_t blocks = std::max<int64_t>(1, (n_steps + GB_K - 1) / GB_K);
+    Workspace *ws = nullptr;
+    int rc = get_workspace(st, 2 * half + (blocks > 1 ? 2 * ihalf : 0), 0, &ws);
+    if (rc != GC_OK) return rc;
+    void *w[2] = {ws->buf, (char *)ws->buf + half};
+    uint32_t *iw[2] = {(uint32_t *)((char *)ws->buf + 2 * half), (uint32_t *)((char *)ws->buf + 2 * half + ihalf)};
+    const void *cur = marker;
+    if (out == marker && blocks == 1) {
+        GC_HIP(hipMemcpyAsync(w[1], marker, (size_t)batch_elems * es, hipMemcpyDeviceToDevice, st));
+        cur = w[1];
+    }
+    const uint32_t *ids = nullptr;
+    for (int64_t b = 0; b < blocks; ++b) {
+        const int kb = (int)std::min<int64_t>(GB_K, n_steps - b * GB_K);   // 0 for a zero-step chain
+        const bool last = b == blocks - 1;
+        SrcBlockArgs a{};
+        a.src = cur;
+        a.mask = mask;
+        a.dst = last ? out : w[b & 1];
+        a.ids_in = ids;
+        a.ids_out = last ? sources : iw[b & 1];
+        a.image_stride = istride;
+        a.pitch = s.pitch;
+        a.width = (int32_t)s.width;
+        a.height = (int32_t)s.height;
+        a.k = kb;
+        const int pr = prof_begin(st, kb);
+        if (dtype == GC_F32) launch_src<float>(op, a, s, n, st);
+        else launch_src<double>(op, a, s, n, st);
+        prof_end(pr, st);
+        GC_HIP(hipGetLastError());
+        cur = a.dst;
+        ids = a.ids_out;
+    }
+    return GC_OK;
+}
+
+// Reverse pass from source ids: grad_marker = 0, then every pixel's
+// upstream gradient onto its leaf.
+static int run_bwd_sources(gc_dtype dtype, const uint32_t *sources, const void *g_out, void *g_marker,
+                           void *g_mask, const gc_shape &s, int32_t n, int64_t stride, hipStream_t st) {
+    if (s.width == 0 || s.height == 0 || n == 0) return GC_OK;
+    const int64_t span = (s.height - 1) * s.pitch + s.width;
+    const int64_t istride = n > 1 ? stride : span;
+    const int64_t total = s.width * s.height * (int64_t)n;
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    SrcScatterArgs a{};
+    a.ids = sources;
+    a.g_out = g_out;
+    a.g_marker = g_marker;
+    a.g_mask = g_mask;
+    a.image_stride = istride;
+    a.pitch = s.pitch;
+    a.width = (int32_t)s.width;
+    a.height = (int32_t)s.height;
+    a.n_images = n;
+    if (dtype == GC_F32) {
+        hipLaunchKernelGGL(src_zero_kernel<float>, dim3(blocks), dim3(256), 0, st, (float *)g_marker, istride,
+                           s.pitch, a.width, a.height, n);
+        hipLaunchKernelGGL(src_scatter_kernel<float>, dim3(blocks), dim3(256), 0, st, a);
+    } else {
+        hipLaunchKernelGGL(src_zero_kernel<double>, dim3(blocks), dim3(256), 0, st, (double *)g_marker, istride,
+                           s.pitch, a.width, a.height, n);
+        hipLaunchKernelGGL(src_scatter_kernel<double>, dim3(blocks), dim3(256), 0, st, a);
+    }
+    GC_HIP(hipGetLastError());
+    return GC_OK;
+}
+
 }  // namespace geochain
 
 using namespace geochain;
@@ -2201,6 +2292,65 @@ int gc_geodesic_chain_bwd(gc_dtype dtype, gc_op op, const uint8_t *codes, const 
         return fail(GC_ERR_ALIAS, "grad_marker overlaps grad_out or grad_mask");
     return run_bwd(dtype, codes, grad_out, grad_marker, grad_mask, shape, n_images, image_stride, n_steps,
                    (hipStream_t)hip_stream);
+}
+
+// Source ids are element offsets within an image, below 2^31.
+static int validate_sources_shape(const gc_shape &s) {
+    if (s.width > 0 && s.height > 0 && (s.height - 1) * s.pitch + s.width > (int64_t)INT32_MAX)
+        return fail(GC_ERR_UNSUPPORTED, "source ids need images of at most 2^31 - 1 elements per image");
+    return GC_OK;
+}
+
+int gc_geodesic_chain_fwd_sources(gc_dtype dtype, gc_op op, const void *marker, const void *mask, void *out,
+                                  uint32_t *sources, gc_shape shape, int32_t n_images, int64_t image_stride,
+                                  int64_t n_steps, void *hip_stream) {
+    GC_CHECK_DTYPE(dtype);
+    GC_CHECK_OP(op);
+    g_last_error.clear();
+    int rc = validate_batch(dtype, shape, n_images, image_stride, n_steps);
+    if (rc != GC_OK) return rc;
+    rc = validate_sources_shape(shape);
+    if (rc != GC_OK) return rc;
+    const bool empty = shape.width == 0 || shape.height == 0 || n_images == 0;
+    if (empty) return GC_OK;
+    if (!marker || !mask || !out || !sources) return fail(GC_ERR_INVALID_ARG, "null pointer");
+    const size_t es = elem_size(dtype);
+    const auto eo = batch_extent(out, shape, n_images, image_stride, es);
+    const auto es_ = batch_extent(sources, shape, n_images, image_stride, 4);
+    if (overlap(eo, batch_extent(mask, shape, n_images, image_stride, es)))
+        return fail(GC_ERR_ALIAS, "out overlaps mask");
+    if (out != marker && overlap(eo, batch_extent(marker, shape, n_images, image_stride, es)))
+        return fail(GC_ERR_ALIAS, "out partially overlaps marker");
+    if (overlap(es_, eo) || overlap(es_, batch_extent(marker, shape, n_images, image_stride, es)) ||
+        overlap(es_, batch_extent(mask, shape, n_images, image_stride, es)))
+        return fail(GC_ERR_ALIAS, "sources overlaps an image");
+    return run_fwd_sources(dtype, enum_bits(&op), marker, mask, out, sources, shape, n_images, image_stride,
+                           n_steps, (hipStream_t)hip_stream);
+}
+
+int gc_geodesic_chain_bwd_sources(gc_dtype dtype, const uint32_t *sources, const void *grad_out,
+                                  void *grad_marker, void *grad_mask, gc_shape shape, int32_t n_images,
+                                  int64_t image_stride, void *hip_stream) {
+    GC_CHECK_DTYPE(dtype);
+    g_last_error.clear();
+    int rc = validate_batch(dtype, shape, n_images, image_stride, 0);
+    if (rc != GC_OK) return rc;
+    rc = validate_sources_shape(shape);
+    if (rc != GC_OK) return rc;
+    const bool empty = shape.width == 0 || shape.height == 0 || n_images == 0;
+    if (empty) return GC_OK;
+    if (!sources || !grad_out || !grad_marker || !grad_mask) return fail(GC_ERR_INVALID_ARG, "null pointer");
+    const size_t es = elem_size(dtype);
+    const auto egm = batch_extent(grad_marker, shape, n_images, image_stride, es);
+    const auto egk = batch_extent(grad_mask, shape, n_images, image_stride, es);
+    const auto ego = batch_extent(grad_out, shape, n_images, image_stride, es);
+    if (overlap(egm, ego) || overlap(egm, egk) || overlap(egk, ego))
+        return fail(GC_ERR_ALIAS, "grad_marker, grad_mask and grad_out must not overlap");
+    const auto es_ = batch_extent(sources, shape, n_images, image_stride, 4);
+    if (overlap(es_, egm) || overlap(es_, egk) || overlap(es_, ego))
+        return fail(GC_ERR_ALIAS, "sources overlaps a gradient");
+    return run_bwd_sources(dtype, sources, grad_out, grad_marker, grad_mask, shape, n_images, image_stride,
+                           (hipStream_t)hip_stream);
 }
 
 int gc_plan_create(gc_dtype dtype, gc_op op, const gc_item *items, int32_t n_items, gc_plan **plan_out) {

@@ -396,4 +396,182 @@ __global__ __launch_bounds__(GradTile<T>::THREADS) void block_bwd_kernel(GradBlo
     }
 }
 
+// ---------------------------------------------------------------------------
+// Source tracking: the per-step routes composed over a run of steps.
+//
+// Following the codes backward from a pixel p of the state after step n
+// (its code at step n-1, then the code of the pixel that names, ...) ends
+// either at a pixel of the state before step 0, or at a step where the
+// mask won, i.e. at the mask value of some pixel.  That end is p's source:
+// p's value is a copy of it, and the gradient of sum(g * out) reaches that
+// leaf with exactly g(p) through every step's route.  So the marker and
+// mask gradients of n steps are
+//   grad_marker[r] = sum of g(p) over the p whose source is marker pixel r,
+//   grad_mask[r]   = sum of g(p) over the p whose source is mask pixel r,
+// the same sums the step-by-step reverse pass forms, added in another order.
+//
+// block_src_kernel runs up to GB_K steps like block_codes_kernel, carrying
+// with every pixel the id of its source: the element offset of the leaf in
+// its image (y * pitch + x), with SRC_MASK set for a mask leaf.  It takes
+// the same choices as the codes (the first extremal neighbour in raster
+// order, the mask winning ties).  Ids of the state before the first step
+// are the pixels' own offsets (ids_in == null), or those a previous launch
+// wrote.  src_scatter_kernel adds g(p) to the leaf its id names.
+// ---------------------------------------------------------------------------
+constexpr uint32_t SRC_MASK = 0x80000000u;
+
+struct SrcBlockArgs {
+    const void *src;          // state before the block
+    const void *mask;
+    void *dst;                // state after the block (core pixels)
+    const uint32_t *ids_in;   // ids of src, or null: each pixel its own offset
+    uint32_t *ids_out;        // ids of dst
+    int64_t image_stride;     // elements between images (values and ids alike)
+    int64_t pitch;            // elements between rows (values and ids alike)
+    int32_t width, height;
+    int32_t k;                // steps in this launch (<= GB_K)
+};
+
+template <typename T, int OP>
+__global__ __launch_bounds__(GradTile<T>::THREADS) void block_src_kernel(SrcBlockArgs a) {
+    using B = Bounds<T, OP>;
+    using G = GradTile<T>;
+    constexpr int CY = G::CY, NW = G::NW;
+    __shared__ T xv[2][NW][2][GB_RW];          // edge rows' row-pass values
+    __shared__ uint32_t xs[2][NW][2][GB_RW];   // and their source ids
+    const GradBlock blk = grad_block();
+    const int img = blk.img;
+    const T *src = static_cast<const T *>(a.src) + img * a.image_stride;
+    const T *msk = static_cast<const T *>(a.mask) + img * a.image_stride;
+    T *dst = static_cast<T *>(a.dst) + img * a.image_stride;
+    const uint32_t *ids_in = a.ids_in ? a.ids_in + img * a.image_stride : nullptr;
+    uint32_t *ids_out = a.ids_out + img * a.image_stride;
+    const int x0 = blk.bx * GB_CX, y0 = blk.by * CY;  // core origin
+    const int rx0 = x0 - GB_K, ry0 = y0 - GB_K;        // region origin
+    const int x = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wa = w > 0 ? w - 1 : NW - 1, wb = w < NW - 1 ? w + 1 : 0;  // region edge: harmless wrap
+    const int gx = rx0 + x;
+    const bool xin = (unsigned)gx < (unsigned)a.width;
+    const bool col_core = (unsigned)(x - GB_K) < (unsigned)GB_CX;
+
+    T v[GB_WR], m[GB_WR];
+    uint32_t id[GB_WR];
+#pragma unroll
+    for (int r = 0; r < GB_WR; ++r) {
+        const int y = ry0 + w * GB_WR + r;
+        const bool in = xin && (unsigned)y < (unsigned)a.height;
+        const int64_t off = (int64_t)y * a.pitch + gx;
+        v[r] = in ? src[off] : B::bottom();
+        m[r] = in ? msk[off] : B::bottom();
+        // outside the image: never chosen (its value never wins), any id
+        id[r] = in ? (ids_in ? ids_in[off] : (uint32_t)off) : 0u;
+    }
+
+    const int k = a.k;
+    for (int s = 0; s < k; ++s) {
+        const int par = s & 1;
+        const bool busy = gb_wave_busy<CY>(w, k, s);
+        T h[GB_WR];
+        uint32_t hs[GB_WR];
+        if (busy) {
+            // row pass: the first of (x-1, x, x+1) equal to their extremum
+#pragma unroll
+            for (int r = 0; r < GB_WR; ++r) {
+                const T c = v[r];
+                const T left = gb_shift<DPP_WAVE_SHR1>(c);
+                const T right = gb_shift<DPP_WAVE_SHL1>(c);
+                const uint32_t il = (uint32_t)gb_shift<DPP_WAVE_SHR1>((int)id[r]);
+                const uint32_t ir = (uint32_t)gb_shift<DPP_WAVE_SHL1>((int)id[r]);
+                const T best = extremum<OP>(extremum<OP>(left, c), right);
+                h[r] = best;
+                hs[r] = left == best ? il : (c == best ? id[r] : ir);
+            }
+            xv[par][w][0][x] = h[0];
+            xs[par][w][0][x] = hs[0];
+            xv[par][w][1][x] = h[GB_WR - 1];
+            xs[par][w][1][x] = hs[GB_WR - 1];
+        }
+        __syncthreads();
+        if (busy) {
+            const T ha = xv[par][wa][1][x], hb = xv[par][wb][0][x];
+            const uint32_t sa = xs[par][wa][1][x], sb = xs[par][wb][0][x];
+            // column pass (rows y-1, y, y+1 in that order), then the clamp
+            // (the mask wins ties); one register array of ids per step
+            uint32_t nid[GB_WR];
+#pragma unroll
+            for (int r = 0; r < GB_WR; ++r) {
+                const T hu = r == 0 ? ha : h[r - 1];
+                const uint32_t su = r == 0 ? sa : hs[r - 1];
+                const T hd = r == GB_WR - 1 ? hb : h[r + 1];
+                const uint32_t sd = r == GB_WR - 1 ? sb : hs[r + 1];
+                const T best = extremum<OP>(extremum<OP>(hu, h[r]), hd);
+                const uint32_t sb_ = hu == best ? su : (h[r] == best ? hs[r] : sd);
+                const bool mask_wins = OP == OP_DILATE ? !(best < m[r]) : !(best > m[r]);
+                const int64_t off = (int64_t)(ry0 + w * GB_WR + r) * a.pitch + gx;
+                v[r] = mask_wins ? m[r] : best;
+                nid[r] = mask_wins ? (SRC_MASK | (uint32_t)off) : sb_;
+            }
+#pragma unroll
+            for (int r = 0; r < GB_WR; ++r) id[r] = nid[r];
+        }
+    }
+    // core of the state after the block, with its ids
+    if (col_core && xin) {
+#pragma unroll
+        for (int r = 0; r < GB_WR; ++r) {
+            const int ly = w * GB_WR + r, y = ry0 + ly;
+            if ((unsigned)(ly - GB_K) < (unsigned)CY && y < a.height) {
+                const int64_t off = (int64_t)y * a.pitch + gx;
+                dst[off] = v[r];
+                ids_out[off] = id[r];
+            }
+        }
+    }
+}
+
+struct SrcScatterArgs {
+    const uint32_t *ids;      // source of every pixel of the state after the run
+    const void *g_out;        // upstream gradient (that state's gradient)
+    void *g_marker;           // gradient of the state before the run: zero on entry
+    void *g_mask;             // mask gradient, accumulated
+    int64_t image_stride, pitch;
+    int32_t width, height, n_images;
+};
+
+// Zeroes the images' pixels (row by row; padding untouched).
+template <typename T>
+__global__ void src_zero_kernel(T *p, int64_t image_stride, int64_t pitch, int32_t width, int32_t height,
+                                int32_t n_images) {
+    const int64_t per = (int64_t)width * height;
+    const int64_t total = per * n_images;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = i / per, r = i % per;
+        p[b * image_stride + (r / width) * pitch + r % width] = T(0);
+    }
+}
+
+// g(p) onto the leaf p's id names.  The additions to one leaf happen in an
+// unspecified order (hardware atomics), so results may differ between runs
+// in the last bits.
+template <typename T>
+__global__ void src_scatter_kernel(SrcScatterArgs a) {
+    const int64_t per = (int64_t)a.width * a.height;
+    const int64_t total = per * a.n_images;
+    const T *g = static_cast<const T *>(a.g_out);
+    T *gf = static_cast<T *>(a.g_marker);
+    T *gm = static_cast<T *>(a.g_mask);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = i / per, r = i % per;
+        const int64_t off = b * a.image_stride + (r / a.width) * a.pitch + r % a.width;
+        const uint32_t id = a.ids[off];
+        const T gv = g[off];
+        if (gv == T(0)) continue;
+        const int64_t leaf = b * a.image_stride + (int64_t)(id & ~SRC_MASK);
+        unsafeAtomicAdd((id & SRC_MASK) ? gm + leaf : gf + leaf, gv);
+    }
+}
+
 }  // namespace geochain

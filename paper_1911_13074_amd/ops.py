@@ -491,3 +491,69 @@ def geodesic_chain_bwd(op, codes, grad_out, grad_mask, grad_marker=None):
                                        _stream(grad_out))
     abi.check(st, "gc_geodesic_chain_bwd")
     return grad_marker
+
+
+def _check_sources(ref: torch.Tensor, sources, names: str) -> None:
+    """sources: int32 with ref's shape, strides and device (the C ABI reads
+    them as uint32 with the images' layout)."""
+    if not isinstance(sources, torch.Tensor):
+        raise TypeError(f"{names}: sources must be a torch.Tensor")
+    if sources.dtype != torch.int32 or sources.shape != ref.shape or sources.device != ref.device:
+        raise ValueError(f"{names}: sources must be int32 of shape {tuple(ref.shape)} on {ref.device} "
+                         f"(got {sources.dtype} {tuple(sources.shape)} on {sources.device})")
+    if sources.numel() > 0 and any(n > 1 and a != b for n, a, b in zip(ref.shape, sources.stride(), ref.stride())):
+        raise ValueError(f"{names}: sources strides differ ({sources.stride()} vs {ref.stride()})")
+
+
+def geodesic_chain_fwd_sources(op, marker, mask, n_steps, out=None, sources=None):
+    """n_steps geodesic steps that also give each output pixel its source:
+    the element offset (y * pitch + x) of the marker pixel, or with the top
+    bit set of the mask pixel, whose value it carries.
+
+    marker, mask: (H, W) or (B, H, W) float32/float64 with the same layout.
+    Returns (out, sources), sources int32 with marker's layout (the top bit
+    makes mask sources negative).
+    """
+    opc = _op_code(op)
+    n_steps = int(n_steps)
+    _, b, stride, shape = _batch_view(marker, "marker")
+    _batch_view(mask, "mask")
+    _check_float_images(("marker", marker), ("mask", mask))
+    _check_batch_like(marker, mask, "marker/mask")
+    if out is not None:
+        _check_batch_like(marker, out, "marker/out")
+    if sources is not None:
+        _check_sources(marker, sources, "marker/sources")
+    _on_gpu(marker, "marker")
+    if out is None:
+        out = torch.empty_strided(marker.shape, marker.stride(), dtype=marker.dtype, device=marker.device)
+    if sources is None:
+        sources = torch.empty_strided(marker.shape, marker.stride(), dtype=torch.int32, device=marker.device)
+    with torch.cuda.device(marker.device):
+        st = abi.gc_geodesic_chain_fwd_sources(_dtype_code(marker), opc, _ptr(marker), _ptr(mask), _ptr(out),
+                                               _ptr(sources), shape, b, stride, n_steps, _stream(marker))
+    abi.check(st, "gc_geodesic_chain_fwd_sources")
+    return out, sources
+
+
+def geodesic_chain_bwd_sources(sources, grad_out, grad_mask, grad_marker=None):
+    """Reverse pass through source ids from geodesic_chain_fwd_sources:
+    returns the gradient w.r.t. the state before the first step and adds
+    the mask's gradient into grad_mask.  grad_mask, sources (and a given
+    grad_marker) must have grad_out's layout."""
+    _, b, stride, shape = _batch_view(grad_out, "grad_out")
+    _check_float_images(("grad_out", grad_out))
+    _check_batch_like(grad_out, grad_mask, "grad_out/grad_mask")
+    _check_sources(grad_out, sources, "grad_out/sources")
+    if grad_marker is not None:
+        _check_batch_like(grad_out, grad_marker, "grad_out/grad_marker")
+    _on_gpu(grad_out, "grad_out")
+    if grad_marker is None:
+        grad_marker = torch.empty_strided(grad_out.shape, grad_out.stride(), dtype=grad_out.dtype,
+                                          device=grad_out.device)
+    with torch.cuda.device(grad_out.device):
+        st = abi.gc_geodesic_chain_bwd_sources(_dtype_code(grad_out), _ptr(sources), _ptr(grad_out),
+                                               _ptr(grad_marker), _ptr(grad_mask), shape, b, stride,
+                                               _stream(grad_out))
+    abi.check(st, "gc_geodesic_chain_bwd_sources")
+    return grad_marker

@@ -1,9 +1,11 @@
 """GPU parity of the differentiable chain: per-step codes bit-exact against
 the oracle's tie rule, the reverse gather against the oracle's scatter
-(float64: same summation order; float32: 1e-5 relative), exact finite
-differences on tie-free inputs, checkpointing invariance, and the
-16 x 1024 x 1024 float32 200-step workload: every image's forward and
-both gradients checked against the oracle."""
+(float64: same summation order; float32: 1e-5 relative), source ids
+bit-exact against the ends of the oracle's code paths, the reverse pass
+through them against the oracle's scatter (float64: 1e-12; float32: 1e-5),
+exact finite differences on tie-free inputs for both methods, checkpointing
+invariance, and the 16 x 1024 x 1024 float32 200-step workload: every
+image's forward and both gradients checked against the oracle."""
 import numpy as np
 import pytest
 import torch
@@ -81,8 +83,9 @@ def test_reverse_gather_float32(op):
         np.testing.assert_allclose(got, ref, rtol=1e-5, atol=1e-5 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("method", ["sources", "codes"])
 @pytest.mark.parametrize("op", OPS)
-def test_autograd_exact_finite_differences(op):
+def test_autograd_exact_finite_differences(op, method):
     # Integer leaves, all distinct (no ties anywhere); eps = 1/4 and integer
     # upstream gradients keep every quantity exact in float64.
     shape, n = (6, 7), 5
@@ -92,7 +95,7 @@ def test_autograd_exact_finite_differences(op):
     g = np.random.default_rng(2).integers(-4, 5, size=shape).astype(np.float64)
     F = dev(f).requires_grad_(True)
     M = dev(m).requires_grad_(True)
-    y = gc.geodesic_chain(F, M, n, op=op, checkpoint_every=2)
+    y = gc.geodesic_chain(F, M, n, op=op, checkpoint_every=2, method=method)
     (y * dev(g)).sum().backward()
     chain = gc.geodesic_dilate_chain if op == "dilate" else gc.geodesic_erode_chain
 
@@ -116,7 +119,7 @@ def test_checkpointing_does_not_change_gradients():
     for ck in (1, 7, 32, 1000):
         F = dev(f).requires_grad_(True)
         M = dev(m).requires_grad_(True)
-        (gc.geodesic_chain(F, M, n, checkpoint_every=ck) * g).sum().backward()
+        (gc.geodesic_chain(F, M, n, checkpoint_every=ck, method="codes") * g).sum().backward()
         grads.append((host(F.grad), host(M.grad)))
     for a, b in grads[1:]:
         assert np.array_equal(a, grads[0][0]) and np.array_equal(b, grads[0][1])
@@ -124,19 +127,20 @@ def test_checkpointing_does_not_change_gradients():
     assert np.array_equal(grads[0][0], ref_gf) and np.array_equal(grads[0][1], ref_gm)
 
 
-def test_batched_images_and_zero_steps():
+@pytest.mark.parametrize("method", ["sources", "codes"])
+def test_batched_images_and_zero_steps(method):
     f, m = rand_pair((3, 40, 50), np.float32, seed=8)
     F = dev(f).requires_grad_(True)
     M = dev(m).requires_grad_(True)
     g = np.random.default_rng(1).standard_normal((3, 40, 50)).astype(np.float32)
-    (gc.geodesic_chain(F, M, 17, op="erode", checkpoint_every=5) * dev(g)).sum().backward()
+    (gc.geodesic_chain(F, M, 17, op="erode", checkpoint_every=5, method=method) * dev(g)).sum().backward()
     for b in range(3):
         rf, rm = oracle.chain_vjp(oracle.ERODE, f[b], m[b], 17, g[b])
         np.testing.assert_allclose(host(F.grad)[b], rf, rtol=1e-5, atol=1e-5)
         np.testing.assert_allclose(host(M.grad)[b], rm, rtol=1e-5, atol=1e-5)
     F0 = dev(f).requires_grad_(True)
     M0 = dev(m).requires_grad_(True)
-    (gc.geodesic_chain(F0, M0, 0) * dev(g)).sum().backward()
+    (gc.geodesic_chain(F0, M0, 0, method=method) * dev(g)).sum().backward()
     assert np.array_equal(host(F0.grad), g) and not host(M0.grad).any()
 
 
@@ -148,7 +152,7 @@ def differentiable_workload():
     f, m, g = workloads.differentiable_f32()
     F = dev(f).requires_grad_(True)
     M = dev(m).requires_grad_(True)
-    y = gc.geodesic_chain(F, M, 200, op="dilate", checkpoint_every=32)
+    y = gc.geodesic_chain(F, M, 200, op="dilate", checkpoint_every=32, method="sources")
     (y * dev(g)).sum().backward()
     res = (f, m, g, host(y), host(F.grad), host(M.grad))
     del F, M, y
@@ -178,3 +182,104 @@ def test_differentiable_workload_gradient_mass(differentiable_workload):
     _, _, g, _, gf, gm = differentiable_workload
     np.testing.assert_allclose(gf.astype(np.float64).sum() + gm.astype(np.float64).sum(),
                                g.astype(np.float64).sum(), rtol=1e-4)
+
+
+# ---- source ids -------------------------------------------------------------
+def sources_from_codes(codes):
+    """Ends of the oracle's code paths: for every pixel of the final state,
+    follow its code at the last step, then the code of the pixel it names at
+    the step before, ..., to a pixel of the initial state or to a step where
+    the mask won.  Returns int32 ids: y * X + x, with the top bit set for a
+    mask pixel (the layout of a dense image)."""
+    n, Y, X = codes.shape
+    yy, xx = np.meshgrid(np.arange(Y), np.arange(X), indexing="ij")
+    yy, xx = yy.ravel().copy(), xx.ravel().copy()
+    at_mask = np.zeros(Y * X, dtype=bool)
+    for t in range(n - 1, -1, -1):
+        live = ~at_mask
+        c = codes[t][yy[live], xx[live]].astype(np.int64)
+        won = c == 9
+        idx = np.flatnonzero(live)
+        at_mask[idx[won]] = True
+        moving = idx[~won]
+        cm = c[~won]
+        yy[moving] += cm // 3 - 1
+        xx[moving] += cm % 3 - 1
+    ids = (yy * X + xx).astype(np.uint32)
+    ids[at_mask] |= np.uint32(0x80000000)
+    return ids.view(np.int32).reshape(Y, X)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("shape,levels,n", [((1, 1), None, 3), ((1, 70), 3, 9), ((33, 1), 3, 17),
+                                            ((37, 129), 4, 9), ((70, 65), None, 8), ((130, 200), 6, 25),
+                                            ((61, 97), 2, 40)])
+def test_sources_match_oracle_paths(dtype, op, shape, levels, n):
+    """Source ids are bit-exact against the ends of the oracle's code paths
+    (one launch per 8 steps, so 9, 17, 25 and 40 steps chain the ids through
+    several launches; few levels give many ties)."""
+    f, m = rand_pair(shape, dtype, seed=shape[0] * 7 + shape[1] + n, levels=levels)
+    out, src = gc.geodesic_chain_fwd_sources(op, dev(f), dev(m), n)
+    ref_out, ref_codes = oracle.chain_codes(code_of(op), f, n, m)
+    assert np.array_equal(host(out), ref_out)
+    assert np.array_equal(host(src), sources_from_codes(ref_codes))
+
+
+def test_sources_pitched_batch_and_zero_steps():
+    """A batch of three pitched images (ids are offsets y * pitch + x within
+    each image) and a zero-step chain (every pixel its own source)."""
+    rng = np.random.default_rng(17)
+    big_f = torch.zeros((3, 50, 80), dtype=torch.float64, device="cuda")
+    big_m = torch.zeros_like(big_f)
+    f = rng.integers(0, 5, size=(3, 50, 70)).astype(np.float64)
+    m = rng.integers(0, 5, size=(3, 50, 70)).astype(np.float64)
+    F, M = big_f[:, :, :70], big_m[:, :, :70]
+    F.copy_(dev(f))
+    M.copy_(dev(m))
+    out, src = gc.geodesic_chain_fwd_sources("dilate", F, M, 13)
+    s = host(src).view(np.uint32)
+    for b in range(3):
+        _, codes = oracle.chain_codes(oracle.DILATE, f[b], 13, m[b])
+        ref = sources_from_codes(codes).view(np.uint32)
+        pos = ref & 0x7FFFFFFF
+        want = (pos // 70) * 80 + pos % 70 | (ref & 0x80000000)
+        assert np.array_equal(s[b], want), f"image {b}"
+    _, src0 = gc.geodesic_chain_fwd_sources("erode", dev(f[0]), dev(m[0]), 0)
+    assert np.array_equal(host(src0), np.arange(50 * 70, dtype=np.int32).reshape(50, 70))
+
+
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("dtype,levels", [(np.float64, None), (np.float64, 5), (np.float32, None), (np.float32, 4)])
+def test_reverse_pass_through_sources(op, dtype, levels):
+    """The scatter through source ids against the oracle's step-by-step
+    scatter: the same contributions added in another order (float64 to
+    1e-12, float32 to 1e-5 of the largest magnitude); the mask gradient is
+    accumulated onto what grad_mask held."""
+    shape, n = (96, 131), 37
+    f, m = rand_pair(shape, dtype, seed=29, levels=levels)
+    g = np.random.default_rng(6).standard_normal(shape).astype(dtype)
+    _, src = gc.geodesic_chain_fwd_sources(op, dev(f), dev(m), n)
+    prior = np.random.default_rng(7).standard_normal(shape).astype(dtype)
+    gm = dev(prior.copy())
+    gf = gc.geodesic_chain_bwd_sources(src, dev(g), gm)
+    ref_gf, ref_gm = oracle.chain_vjp(code_of(op), f, m, n, g)
+    tol = 1e-12 if dtype == np.float64 else 1e-5
+    np.testing.assert_allclose(host(gf), ref_gf, rtol=tol, atol=tol * np.abs(ref_gf).max())
+    np.testing.assert_allclose(host(gm) - prior, ref_gm, rtol=tol, atol=tol * max(np.abs(ref_gm).max(), 1))
+
+
+def test_methods_agree_on_checkpointing():
+    """Both methods, several checkpoint spacings, one float64 chain: the
+    gradients agree with the oracle's to 1e-12."""
+    shape, n = (90, 110), 100
+    f, m = rand_pair(shape, np.float64, seed=21, levels=7)
+    g = dev(np.random.default_rng(5).standard_normal(shape))
+    ref_gf, ref_gm = oracle.chain_vjp(oracle.DILATE, f, m, n, host(g))
+    for method in ("sources", "codes"):
+        for ck in (1, 9, 32, 1000):
+            F = dev(f).requires_grad_(True)
+            M = dev(m).requires_grad_(True)
+            (gc.geodesic_chain(F, M, n, checkpoint_every=ck, method=method) * g).sum().backward()
+            np.testing.assert_allclose(host(F.grad), ref_gf, rtol=1e-12, atol=1e-12 * np.abs(ref_gf).max())
+            np.testing.assert_allclose(host(M.grad), ref_gm, rtol=1e-12, atol=1e-12 * np.abs(ref_gm).max())

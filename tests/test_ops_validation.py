@@ -74,3 +74,46 @@ def test_backward_entry_point_checks_op():
     # empty batch: valid, nothing to do
     assert abi.gc_geodesic_chain_bwd(abi.GC_F64, abi.GC_ERODE, None, None, None, None, sh, 0, 64, 3,
                                      None) == abi.GC_OK
+
+
+@pytest.mark.parametrize("make,msg", [
+    (lambda: gc.geodesic_chain_fwd_sources("dilate", f32(8, 9), f32(8, 9), 3,
+                                           sources=torch.zeros((8, 9), dtype=torch.int64)), "sources must be int32"),
+    (lambda: gc.geodesic_chain_fwd_sources("dilate", f32(8, 9), f32(8, 9), 3,
+                                           sources=torch.zeros((8, 8), dtype=torch.int32)), "sources must be int32"),
+    (lambda: gc.geodesic_chain_fwd_sources("dilate", f32(8, 9), f32(8, 9), 3,
+                                           sources=torch.zeros((9, 8), dtype=torch.int32).t()), "strides differ"),
+    (lambda: gc.geodesic_chain_fwd_sources("dilate", f32(8, 9), f32(8, 10), 3), "shape, dtype and device"),
+    (lambda: gc.geodesic_chain_fwd_sources("open", f32(8, 9), f32(8, 9), 3), "op is"),
+    (lambda: gc.geodesic_chain_bwd_sources(torch.zeros((8, 9), dtype=torch.int32), f32(8, 9),
+                                           torch.zeros((8, 9), dtype=torch.float64)), "shape, dtype and device"),
+    (lambda: gc.geodesic_chain_bwd_sources(torch.zeros((2, 8, 9), dtype=torch.int32), f32(8, 9), f32(8, 9)),
+     "sources must be int32"),
+    (lambda: gc.geodesic_chain_bwd_sources(torch.zeros((8, 9), dtype=torch.int32), f32(8, 9), f32(8, 9),
+                                           grad_marker=f32(9, 8).t()), "strides differ"),
+])
+def test_source_wrappers_refuse_mismatched_layouts(make, msg):
+    with pytest.raises((ValueError, TypeError), match=msg):
+        make()
+
+
+def test_source_entry_points_validate_on_the_host():
+    """Null pointers, unknown op, integer dtype and images beyond 2^31 - 1
+    elements are refused before any HIP call."""
+    FAKE = 1 << 40
+    far = 1 << 44
+    s = abi.gc_shape(9, 8, 9)
+    assert abi.gc_geodesic_chain_fwd_sources(abi.GC_F32, abi.GC_DILATE, FAKE, FAKE + far, FAKE + 2 * far, None,
+                                             s, 1, 0, 3, None) == abi.GC_ERR_INVALID_ARG
+    assert abi.gc_geodesic_chain_fwd_sources(abi.GC_F32, 4, FAKE, FAKE + far, FAKE + 2 * far, FAKE + 3 * far,
+                                             s, 1, 0, 3, None) == abi.GC_ERR_INVALID_ARG
+    assert abi.gc_geodesic_chain_fwd_sources(abi.GC_U8, abi.GC_DILATE, FAKE, FAKE + far, FAKE + 2 * far,
+                                             FAKE + 3 * far, s, 1, 0, 3, None) == abi.GC_ERR_UNSUPPORTED
+    big = abi.gc_shape(1 << 16, 1 << 15, 1 << 16)   # 2^31 elements
+    assert abi.gc_geodesic_chain_fwd_sources(abi.GC_F32, abi.GC_DILATE, FAKE, FAKE + far, FAKE + 2 * far,
+                                             FAKE + 3 * far, big, 1, 0, 3, None) == abi.GC_ERR_UNSUPPORTED
+    assert "2^31" in abi.last_error()
+    assert abi.gc_geodesic_chain_bwd_sources(abi.GC_F64, FAKE, FAKE + far, FAKE + far, FAKE + 2 * far,
+                                             s, 1, 0, None) == abi.GC_ERR_ALIAS
+    assert abi.gc_geodesic_chain_bwd_sources(abi.GC_F64, None, FAKE + far, FAKE + 2 * far, FAKE + 3 * far,
+                                             s, 1, 0, None) == abi.GC_ERR_INVALID_ARG
