@@ -55,7 +55,60 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB, 5 times "
                          "(reference dispatch for HBM byte counters), then exit")
+    ap.add_argument("--batch-shapes", action="store_true",
+                    help="only time the 64-image batch split into size classes under every launch "
+                         "shape (tile family x steps per block), print one JSON line, then exit")
     return ap.parse_args()
+
+
+def batch_shape_study(gc, dev):
+    """Per size class of the 64-image uneven batch (longest side 128-511,
+    512-1023, 1024-1535, 1536-2048): the time of a plan of that class's
+    images under every launch shape, the best of them, and the plan-wide
+    built-in shape; then the whole batch under the built-in shape.  If the
+    classes' best shapes saved little against the plan-wide one, a plan
+    with per-class shapes could save no more than that."""
+    batch = workloads.batch_u8()
+    items = [(torch.from_numpy(it.marker).to(dev), torch.from_numpy(it.mask).to(dev), it.n_steps)
+             for it in batch.items]
+    bounds = [(128, 512), (512, 1024), (1024, 1536), (1536, 2049)]
+    shapes = [(fam, k) for fam in (2, 0, 4, 3) for k in (12, 16, 20, 24, 28) if not (fam in (3, 4) and k > 28)]
+
+    def plan_ms(sel, fam, k):
+        gc.set_tuning(k, fam)
+        try:
+            plan = gc.BatchPlan("dilate", [items[i] for i in sel])
+        finally:
+            gc.set_tuning(0, -1)
+        ms = timed(plan.launch, 4, 1)
+        plan.status()
+        plan.close()
+        return ms
+
+    classes = []
+    total_builtin = 0.0
+    total_best = 0.0
+    for lo, hi in bounds:
+        sel = [i for i, it in enumerate(batch.items) if lo <= max(it.marker.shape) < hi]
+        if not sel:
+            continue
+        px_steps = sum(batch.items[i].marker.size * batch.items[i].n_steps for i in sel)
+        times = {f"{fam}/{k}": round(plan_ms(sel, fam, k), 3) for fam, k in shapes}
+        builtin = plan_ms(sel, -1, 0)
+        best = min(times, key=times.get)
+        total_builtin += builtin
+        total_best += times[best]
+        classes.append({"longest_side": [lo, hi - 1], "images": len(sel), "px_steps": px_steps,
+                        "builtin_ms": round(builtin, 3), "best_shape": best, "best_ms": times[best],
+                        "ms_by_shape": times})
+    plan = gc.BatchPlan("dilate", items)
+    whole = timed(plan.launch, 4, 1)
+    plan.status()
+    plan.close()
+    return {"classes": classes, "sum_builtin_ms": round(total_builtin, 3), "sum_best_ms": round(total_best, 3),
+            "whole_batch_builtin_ms": round(whole, 3),
+            "shape_key": "tile family / steps per block (family 2 = 128x128 16 waves, 0 = 128x128 8 waves, "
+                         "4 = 96x96 16 waves, 3 = 96x96 8 waves)"}
 
 
 def timed(fn, steps, warmup):
@@ -285,6 +338,10 @@ def main():
         print(json.dumps({"copy_calibration_bytes": n, "copies": 5}), flush=True)
         return
     import paper_1911_13074_amd as gc
+
+    if args.batch_shapes:
+        print(json.dumps({"batch_shape_study": batch_shape_study(gc, dev)}), flush=True)
+        return
 
     N, S = args.chain, args.size
     f, m = workloads.headline_u8_dilation(size=S)

@@ -119,6 +119,18 @@ int gc_geodesic_erode_chain(gc_dtype dtype, const void *marker, const void *mask
                             void *hip_stream);
 
 /* ---------------------------------------------------------------------
+ * A batch of geodesic chains of equal shape (Eq. 3-4), all advanced by the
+ * same launches: what gc_geodesic_{dilate,erode}_chain computes for each of
+ * n_images images, image i at element offset i * image_stride from marker,
+ * mask and out (image_stride >= (height - 1) * pitch + width when
+ * n_images > 1; n_images <= 65535).  op = GC_DILATE or GC_ERODE.  out may
+ * equal marker; out must not overlap mask, nor partially overlap marker.
+ * ------------------------------------------------------------------- */
+int gc_geodesic_chain_batch(gc_dtype dtype, gc_op op, const void *marker, const void *mask,
+                            void *out, gc_shape shape, int32_t n_images, int64_t image_stride,
+                            int64_t n_steps, void *hip_stream);
+
+/* ---------------------------------------------------------------------
  * The geodesic chain for callers that cannot allocate device memory:
  * code recorded into a HIP graph by stream capture, serving loops that
  * must not allocate, harnesses that forbid hipMalloc.

@@ -15,6 +15,7 @@ from .ops import (  # noqa: F401
     dilate_chain,
     dome,
     erode_chain,
+    geodesic_chain_batch,
     geodesic_chain_bwd,
     geodesic_chain_bwd_sources,
     geodesic_chain_fwd_sources,

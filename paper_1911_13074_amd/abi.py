@@ -52,6 +52,7 @@ SIGNATURES = {
     "gc_last_error": (ctypes.c_char_p, []),
     "gc_geodesic_dilate_chain": (ctypes.c_int, [_DT, _VP, _VP, _VP, gc_shape, _I64, _VP]),
     "gc_geodesic_erode_chain": (ctypes.c_int, [_DT, _VP, _VP, _VP, gc_shape, _I64, _VP]),
+    "gc_geodesic_chain_batch": (ctypes.c_int, [_DT, _DT, _VP, _VP, _VP, gc_shape, _I32, _I64, _I64, _VP]),
     "gc_geodesic_chain_noalloc": (ctypes.c_int, [_DT, _DT, _VP, _VP, _VP, gc_shape, _I64, _VP]),
     "gc_dilate_chain": (ctypes.c_int, [_DT, _VP, _VP, gc_shape, _I64, _VP]),
     "gc_erode_chain": (ctypes.c_int, [_DT, _VP, _VP, gc_shape, _I64, _VP]),

@@ -33,16 +33,13 @@ class GeodesicChainFunction(torch.autograd.Function):
         mask = mask.contiguous()
         imgs_m = marker if marker.dim() == 3 else marker.unsqueeze(0)
         imgs_k = mask if mask.dim() == 3 else mask.unsqueeze(0)
-        chain = ops.geodesic_dilate_chain if op == "dilate" else ops.geodesic_erode_chain
         ckpts = [marker]
         cur = imgs_m
         starts = list(range(0, n_steps, seg))
         for i, s0 in enumerate(starts):
             n = min(seg, n_steps - s0)
-            nxt = torch.empty_like(cur)
-            for b in range(cur.shape[0]):
-                chain(cur[b], imgs_k[b], n, out=nxt[b])
-            cur = nxt
+            # all images of the batch in the same launches
+            cur = ops.geodesic_chain_batch(op, cur, imgs_k, n)
             if i + 1 < len(starts):
                 ckpts.append(cur.view_as(marker))
         # the last segment's state is a fresh tensor that no checkpoint holds

@@ -165,6 +165,8 @@ struct BlockArgs {
     int32_t core_x, core_y;
     int32_t tiles_x;
     int32_t tile0;         // tile of the launch's first workgroup (large images take several launches)
+    int32_t tiles_per_image;   // batches of equal images: tiles of one image (0: a single image)
+    int64_t image_stride;      // batches: elements between images of src, mask and dst
     uint32_t *change_word;       // reconstruction: OR of per-step change bits
     const uint32_t *prev_word;   // reconstruction: predecessor's word (or null)
     uint32_t prev_full;          // value prev_word holds if every step changed
@@ -1248,7 +1250,17 @@ __global__ __launch_bounds__(64 * NW) void chain_block_kernel(BlockArgs a) {
         // The image stopped changing in an earlier launch: nothing to do.
         if (*a.prev_word != a.prev_full) return;
     }
-    const int tile = a.tile0 + xcd_tile(blockIdx.x, gridDim.x);
+    int tile = a.tile0 + xcd_tile(blockIdx.x, gridDim.x);
+    BlockArgs b = a;
+    if (a.tiles_per_image > 0) {
+        // a batch: tiles of image i follow those of image i - 1
+        const int img = tile / a.tiles_per_image;
+        tile -= img * a.tiles_per_image;
+        const int64_t off = (int64_t)img * a.image_stride;
+        b.src = static_cast<const T *>(a.src) + off;
+        b.mask = a.mask ? static_cast<const T *>(a.mask) + off : nullptr;
+        b.dst = static_cast<T *>(a.dst) + off;
+    }
     const int tx = tile % a.tiles_x;
     const int ty = tile / a.tiles_x;
     const int rx0 = tx * a.core_x - a.halo;
@@ -1257,7 +1269,7 @@ __global__ __launch_bounds__(64 * NW) void chain_block_kernel(BlockArgs a) {
     __shared__ __attribute__((aligned(16))) R xch[2][NW][2 * G][lanes_per_group<G>() * CW];
     __shared__ __attribute__((aligned(16))) uint8_t stage[stage_bytes<T, CW, RPW, NW, G, true>()];
     const uint32_t bits =
-        chain_block_dispatch<T, OP, MODE, DETECT, CW, RPW, NW, G, false, true>(a, rx0, ry0, xch, stage);
+        chain_block_dispatch<T, OP, MODE, DETECT, CW, RPW, NW, G, false, true>(b, rx0, ry0, xch, stage);
     if constexpr (DETECT) {
         if (bits != 0 && (threadIdx.x & 63) == 0) atomicOr(a.change_word, bits);
     }

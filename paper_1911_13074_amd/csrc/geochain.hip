@@ -662,16 +662,31 @@ static int run_window(gc_dtype dtype, int op, const void *in, void *out, const g
 // fixed_ws: a caller-chosen work buffer of fixed_bytes bytes in place of
 // the stream's workspace (the entry point that allocates nothing); such
 // calls also skip the measurement hook, whose events are allocated.
+// Batches (n_images > 1): images of one shape at image_stride elements from
+// each other, all advanced by the same launches (one workgroup per tile of
+// every image).
+static int copy_batch(void *dst, const void *src, const gc_shape &s, size_t es, hipStream_t st, int32_t n_images,
+                      int64_t image_stride) {
+    for (int32_t i = 0; i < n_images; ++i) {
+        const size_t off = (size_t)i * (size_t)image_stride * es;
+        const int rc = copy_image((char *)dst + off, (const char *)src + off, s, es, st);
+        if (rc != GC_OK) return rc;
+    }
+    return GC_OK;
+}
+
 static int run_chain(gc_dtype dtype, int op, int mode, const void *src, const void *mask, void *out,
                      const gc_shape &s, int64_t n, void *stream, void *fixed_ws = nullptr,
-                     size_t fixed_bytes = 0) {
+                     size_t fixed_bytes = 0, int32_t n_images = 1, int64_t image_stride = 0) {
     if (n < 0) return fail(GC_ERR_INVALID_ARG, "n_steps < 0");
-    const bool empty = s.width == 0 || s.height == 0;
+    const bool empty = s.width == 0 || s.height == 0 || n_images == 0;
     const size_t es = elem_size(dtype);
     hipStream_t st = (hipStream_t)stream;
     if (empty) return GC_OK;
-    if (n == 0) return copy_image(out, src, s, es, st);
-    if (mode == MODE_PLAIN && window_path(dtype, s, n)) return run_window(dtype, op, src, out, s, n, stream);
+    if (n_images == 1) image_stride = 0;
+    if (n == 0) return copy_batch(out, src, s, es, st, n_images, image_stride);
+    if (n_images == 1 && mode == MODE_PLAIN && window_path(dtype, s, n))
+        return run_window(dtype, op, src, out, s, n, stream);
 
     const Plan1 p = choose_plan(s, n, false);
     // Launches: L0 - 1 of p.k steps and a last one with the remainder.  In
@@ -694,7 +709,13 @@ static int run_chain(gc_dtype dtype, int op, int mode, const void *src, const vo
         }
         return (int)std::min<int64_t>(p.k, n - i * p.k);
     };
-    const size_t bytes = (size_t)((s.height - 1) * s.pitch + s.width) * es;
+    const size_t bytes = (size_t)((int64_t)(n_images - 1) * image_stride + (s.height - 1) * s.pitch + s.width) * es;
+    {
+        // tile counts of a launch stay in 32 bits
+        const Geometry g = geometry(s, p.fam, p.k);   // the most tiles of any launch
+        if ((int64_t)g.tiles * n_images > (int64_t)INT32_MAX)
+            return fail(GC_ERR_UNSUPPORTED, "%d images of %d tiles each exceed 2^31 - 1 tiles", n_images, g.tiles);
+    }
     void *work = fixed_ws;
     if (fixed_ws) {
         if (bytes > fixed_bytes)
@@ -710,7 +731,7 @@ static int run_chain(gc_dtype dtype, int op, int mode, const void *src, const vo
 
     const void *cur = src;
     if (copy_first) {
-        const int rc = copy_image(work, src, s, es, st);
+        const int rc = copy_batch(work, src, s, es, st, n_images, image_stride);
         if (rc != GC_OK) return rc;
         cur = work;
     }
@@ -733,9 +754,11 @@ static int run_chain(gc_dtype dtype, int op, int mode, const void *src, const vo
         a.core_x = g.core_x;
         a.core_y = g.core_y;
         a.tiles_x = g.tiles_x;
+        a.tiles_per_image = n_images > 1 ? g.tiles : 0;
+        a.image_stride = image_stride;
         LaunchFn fn = pick_launch(dtype, op, mode, false, p.fam);
         const int pr = hook ? prof_begin(st, ki) : -1;
-        fn(a, g.tiles, st);
+        fn(a, g.tiles * n_images, st);
         if (hook) prof_end(pr, st);
         GC_HIP(hipGetLastError());
         cur = dst;
@@ -1921,15 +1944,15 @@ static int run_fwd_sources(gc_dtype dtype, int op, const void *marker, const voi
     return GC_OK;
 }
 
-// Reverse pass from source ids: grad_marker = 0, then every pixel's
-// upstream gradient onto its leaf.
+// Reverse pass from source ids: the own-pixel pass (which also sets every
+// other marker-gradient pixel to zero), then the atomic pass.
 static int run_bwd_sources(gc_dtype dtype, const uint32_t *sources, const void *g_out, void *g_marker,
                            void *g_mask, const gc_shape &s, int32_t n, int64_t stride, hipStream_t st) {
     if (s.width == 0 || s.height == 0 || n == 0) return GC_OK;
     const int64_t span = (s.height - 1) * s.pitch + s.width;
     const int64_t istride = n > 1 ? stride : span;
-    const int64_t total = s.width * s.height * (int64_t)n;
-    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    // x: columns in groups of 256; y: rows, strided; z: images
+    const dim3 grid((unsigned)((s.width + 255) / 256), (unsigned)std::min<int64_t>(s.height, 64), (unsigned)n);
     SrcScatterArgs a{};
     a.ids = sources;
     a.g_out = g_out;
@@ -1941,13 +1964,11 @@ static int run_bwd_sources(gc_dtype dtype, const uint32_t *sources, const void *
     a.height = (int32_t)s.height;
     a.n_images = n;
     if (dtype == GC_F32) {
-        hipLaunchKernelGGL(src_zero_kernel<float>, dim3(blocks), dim3(256), 0, st, (float *)g_marker, istride,
-                           s.pitch, a.width, a.height, n);
-        hipLaunchKernelGGL(src_scatter_kernel<float>, dim3(blocks), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(src_local_kernel<float>, grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL(src_scatter_kernel<float>, grid, dim3(256), 0, st, a);
     } else {
-        hipLaunchKernelGGL(src_zero_kernel<double>, dim3(blocks), dim3(256), 0, st, (double *)g_marker, istride,
-                           s.pitch, a.width, a.height, n);
-        hipLaunchKernelGGL(src_scatter_kernel<double>, dim3(blocks), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(src_local_kernel<double>, grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL(src_scatter_kernel<double>, grid, dim3(256), 0, st, a);
     }
     GC_HIP(hipGetLastError());
     return GC_OK;
@@ -2073,6 +2094,34 @@ int gc_geodesic_chain_noalloc(gc_dtype dtype, gc_op op, const void *marker, cons
     if (rc != GC_OK) return rc;
     return run_chain(dtype, enum_bits(&op), MODE_GEODESIC, marker, mask, out, shape, n_steps, hip_stream, work,
                      NOALLOC_SCRATCH_BYTES);
+}
+
+int gc_geodesic_chain_batch(gc_dtype dtype, gc_op op, const void *marker, const void *mask, void *out,
+                            gc_shape shape, int32_t n_images, int64_t image_stride, int64_t n_steps,
+                            void *hip_stream) {
+    GC_CHECK_DTYPE(dtype);
+    GC_CHECK_OP(op);
+    g_last_error.clear();
+    int rc = validate_shape(dtype, shape);
+    if (rc != GC_OK) return rc;
+    if (n_images < 0) return fail(GC_ERR_INVALID_ARG, "n_images < 0");
+    if (n_images > 65535) return fail(GC_ERR_UNSUPPORTED, "at most 65535 images per call");
+    if (n_steps < 0) return fail(GC_ERR_INVALID_ARG, "n_steps < 0");
+    const bool empty = shape.width == 0 || shape.height == 0 || n_images == 0;
+    if (empty) return GC_OK;
+    const int64_t span = (shape.height - 1) * shape.pitch + shape.width;
+    if (n_images > 1 && image_stride < span)
+        return fail(GC_ERR_INVALID_ARG, "image_stride %lld < image span %lld", (long long)image_stride,
+                    (long long)span);
+    if (!marker || !mask || !out) return fail(GC_ERR_INVALID_ARG, "null pointer");
+    const size_t es = elem_size(dtype);
+    const auto eo = batch_extent(out, shape, n_images, image_stride, es);
+    if (overlap(eo, batch_extent(mask, shape, n_images, image_stride, es)))
+        return fail(GC_ERR_ALIAS, "out overlaps mask");
+    if (out != marker && overlap(eo, batch_extent(marker, shape, n_images, image_stride, es)))
+        return fail(GC_ERR_ALIAS, "out partially overlaps marker");
+    return run_chain(dtype, enum_bits(&op), MODE_GEODESIC, marker, mask, out, shape, n_steps, hip_stream, nullptr, 0,
+                     n_images, image_stride);
 }
 
 static int plain_chain(gc_dtype dtype, int op, const void *in, void *out, gc_shape shape,

@@ -539,37 +539,51 @@ struct SrcScatterArgs {
     int32_t width, height, n_images;
 };
 
-// Zeroes the images' pixels (row by row; padding untouched).
+// The scatter in two passes.  Pass 1 (src_local_kernel) streams over the
+// pixels: the marker gradient of pixel p becomes g(p) if p's source is its
+// own marker pixel and 0 otherwise, and the mask gradient of p gains g(p)
+// if p's source is its own mask pixel; no other pixel of the pass writes
+// there, so these are plain accesses.  Pass 2 (src_scatter_kernel), after
+// it, adds the gradient of every other pixel to the leaf its id names with
+// hardware atomics.  In the chains of a reconstruction most pixels end as
+// copies of their own mask value, so pass 2 has little to do.  Additions
+// into one leaf from several pixels come in no fixed order, so results may
+// differ between runs in the last bits.
+// Grid: x over the columns of a row, y over rows (strided), z = image.
 template <typename T>
-__global__ void src_zero_kernel(T *p, int64_t image_stride, int64_t pitch, int32_t width, int32_t height,
-                                int32_t n_images) {
-    const int64_t per = (int64_t)width * height;
-    const int64_t total = per * n_images;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t b = i / per, r = i % per;
-        p[b * image_stride + (r / width) * pitch + r % width] = T(0);
+__global__ void src_local_kernel(SrcScatterArgs a) {
+    const int64_t base = (int64_t)blockIdx.z * a.image_stride;
+    const T *g = static_cast<const T *>(a.g_out) + base;
+    T *gf = static_cast<T *>(a.g_marker) + base;
+    T *gm = static_cast<T *>(a.g_mask) + base;
+    const uint32_t *ids = a.ids + base;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= a.width) return;
+    for (int y = blockIdx.y; y < a.height; y += gridDim.y) {
+        const uint32_t pos = (uint32_t)((int64_t)y * a.pitch + x);
+        const uint32_t id = ids[pos];
+        const T gv = g[pos];
+        gf[pos] = id == pos ? gv : T(0);
+        if (id == (SRC_MASK | pos) && gv != T(0)) gm[pos] += gv;
     }
 }
 
-// g(p) onto the leaf p's id names.  The additions to one leaf happen in an
-// unspecified order (hardware atomics), so results may differ between runs
-// in the last bits.
 template <typename T>
 __global__ void src_scatter_kernel(SrcScatterArgs a) {
-    const int64_t per = (int64_t)a.width * a.height;
-    const int64_t total = per * a.n_images;
-    const T *g = static_cast<const T *>(a.g_out);
-    T *gf = static_cast<T *>(a.g_marker);
-    T *gm = static_cast<T *>(a.g_mask);
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t b = i / per, r = i % per;
-        const int64_t off = b * a.image_stride + (r / a.width) * a.pitch + r % a.width;
-        const uint32_t id = a.ids[off];
-        const T gv = g[off];
+    const int64_t base = (int64_t)blockIdx.z * a.image_stride;
+    const T *g = static_cast<const T *>(a.g_out) + base;
+    T *gf = static_cast<T *>(a.g_marker) + base;
+    T *gm = static_cast<T *>(a.g_mask) + base;
+    const uint32_t *ids = a.ids + base;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= a.width) return;
+    for (int y = blockIdx.y; y < a.height; y += gridDim.y) {
+        const uint32_t pos = (uint32_t)((int64_t)y * a.pitch + x);
+        const uint32_t id = ids[pos];
+        if ((id & ~SRC_MASK) == pos) continue;  // own pixel: pass 1
+        const T gv = g[pos];
         if (gv == T(0)) continue;
-        const int64_t leaf = b * a.image_stride + (int64_t)(id & ~SRC_MASK);
+        const uint32_t leaf = id & ~SRC_MASK;
         unsafeAtomicAdd((id & SRC_MASK) ? gm + leaf : gf + leaf, gv);
     }
 }

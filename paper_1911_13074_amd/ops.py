@@ -493,6 +493,28 @@ def geodesic_chain_bwd(op, codes, grad_out, grad_mask, grad_marker=None):
     return grad_marker
 
 
+def geodesic_chain_batch(op, marker, mask, n_steps, out=None):
+    """n_steps geodesic dilations ('dilate') or erosions ('erode') of every
+    image of a (B, H, W) batch (or one (H, W) image) under its mask, in one
+    launch per block of steps.  mask (and a given out) must have marker's
+    layout; out may be marker."""
+    opc = _op_code(op)
+    _, b, stride, shape = _batch_view(marker, "marker")
+    _batch_view(mask, "mask")
+    _dtype_code(marker)
+    _check_batch_like(marker, mask, "marker/mask")
+    if out is not None:
+        _check_batch_like(marker, out, "marker/out")
+    _on_gpu(marker, "marker")
+    if out is None:
+        out = torch.empty_strided(marker.shape, marker.stride(), dtype=marker.dtype, device=marker.device)
+    with torch.cuda.device(marker.device):
+        st = abi.gc_geodesic_chain_batch(_dtype_code(marker), opc, _ptr(marker), _ptr(mask), _ptr(out), shape, b,
+                                         stride, int(n_steps), _stream(marker))
+    abi.check(st, "gc_geodesic_chain_batch")
+    return out
+
+
 def _check_sources(ref: torch.Tensor, sources, names: str) -> None:
     """sources: int32 with ref's shape, strides and device (the C ABI reads
     them as uint32 with the images' layout)."""

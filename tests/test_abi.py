@@ -227,3 +227,23 @@ def test_noalloc_chain_refusals():
     # empty images succeed without touching the device
     assert abi.gc_geodesic_chain_noalloc(abi.GC_U8, abi.GC_DILATE, None, None, None,
                                          shape(0, 5, 0), 3, None) == abi.GC_OK
+
+
+def test_batch_chain_refusals():
+    far = 1 << 30
+    s = shape(10, 10, 10)
+    # stride below the image span, too many images, negative count, null mask
+    assert abi.gc_geodesic_chain_batch(abi.GC_U8, abi.GC_DILATE, FAKE, FAKE + far, FAKE + 2 * far, s, 2, 50,
+                                       3, None) == abi.GC_ERR_INVALID_ARG
+    assert abi.gc_geodesic_chain_batch(abi.GC_U8, abi.GC_DILATE, FAKE, FAKE + far, FAKE + 2 * far, s, 70000,
+                                       100, 3, None) == abi.GC_ERR_UNSUPPORTED
+    assert abi.gc_geodesic_chain_batch(abi.GC_F32, abi.GC_ERODE, FAKE, FAKE + far, FAKE + 2 * far, s, -1,
+                                       100, 3, None) == abi.GC_ERR_INVALID_ARG
+    assert abi.gc_geodesic_chain_batch(abi.GC_F64, abi.GC_ERODE, FAKE, None, FAKE + 2 * far, s, 2,
+                                       100, 3, None) == abi.GC_ERR_INVALID_ARG
+    # out overlapping the second image's mask
+    assert abi.gc_geodesic_chain_batch(abi.GC_U8, abi.GC_DILATE, FAKE, FAKE + far, FAKE + far + 150, s, 2,
+                                       100, 3, None) == abi.GC_ERR_ALIAS
+    # empty batches succeed without touching the device
+    assert abi.gc_geodesic_chain_batch(abi.GC_U8, abi.GC_DILATE, None, None, None, s, 0, 0, 3,
+                                       None) == abi.GC_OK
