@@ -146,10 +146,11 @@ def kernel_profile(fn, steps):
 
 PROFILE = os.path.join(ROOT, "profiles", "chain_u8_1024_geodesic_dilation.md")
 PROFILE_SQ = os.path.join(ROOT, "profiles", "chain_u8_1024_sq_counters.md")
-# The profiled kernel's code and its launch shape (tile families, steps per
-# launch, grid): a change to either makes the committed counters stale.
+# The profiled kernel's code (chain_block.hpp) and its launch shapes (tile
+# families, steps per launch, tile geometry and launch wrappers in
+# chain_launch.hpp): a change to either makes the committed counters stale.
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1911_13074_amd", "csrc", f)
-                  for f in ("chain_block.hpp", "geochain.hip")]
+                  for f in ("chain_block.hpp", "chain_launch.hpp")]
 
 
 def profiled_traffic():
