@@ -1486,6 +1486,9 @@ static int plan_build(gc_dtype dtype, int op, const gc_item *items, int32_t n_it
         a.error = p->words_d + 1;
         a.flags = p->words_d + 2;
         a.wait_ticks = PLAN_WAIT_TICKS;
+        // Tests of the error path: GEOCHAIN_PLAN_WAIT_TICKS=<n> bounds the
+        // waits of plans built while it is set to n ticks (0: they fail at once).
+        if (const char *e = getenv("GEOCHAIN_PLAN_WAIT_TICKS")) a.wait_ticks = strtoull(e, nullptr, 10);
         // Consecutive items per ticket (neighbouring tiles of one image, run
         // by one workgroup back to back, share its XCD's L2): about eight
         // tickets per workgroup, at most 4 items each.  Measured on the

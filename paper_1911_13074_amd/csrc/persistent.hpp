@@ -90,6 +90,7 @@ __device__ __forceinline__ bool wait_neighbours(const PersistentArgs &a, const P
     const int nx = tx + dx, ny = ty + dy;
     const bool mine = lane < 9 && nx >= 0 && nx < im.tiles_x && ny >= 0 && ny < im.tiles_y;
     const uint32_t *flag = a.flags + im.flag_base + (mine ? ny * im.tiles_x + nx : 0);
+    if (a.wait_ticks == 0) return false;   // a bound of 0: every wait fails at once (tests of the error path)
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
     for (;;) {
         bool ok = true;

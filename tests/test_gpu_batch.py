@@ -384,3 +384,24 @@ def test_two_plans_at_the_same_time():
     plan_b.status()
     check_items("dilate", a_items, plan_a.outs)
     check_items("erode", b_items, plan_b.outs)
+
+
+def test_wait_bound_reports_and_drains(monkeypatch):
+    """A plan whose dependency waits are bounded at zero (test hook
+    GEOCHAIN_PLAN_WAIT_TICKS=0: every wait fails at once): the launch still
+    drains, gc_plan_status reports GC_ERR_HIP, and a plan built afterwards
+    without the hook is exact again."""
+    items = make_batch(np.uint8, seed=61, count=4, lo=200, hi=400, n_lo=60, n_hi=120)
+    dev_items = [(dev(f), dev(m), n) for f, m, n in items]
+    monkeypatch.setenv("GEOCHAIN_PLAN_WAIT_TICKS", "0")
+    bad = gc.BatchPlan("dilate", dev_items)
+    monkeypatch.delenv("GEOCHAIN_PLAN_WAIT_TICKS")
+    bad.launch()
+    with pytest.raises(abi.GeochainError) as ei:
+        bad.status()
+    assert ei.value.status == abi.GC_ERR_HIP and "bound" in str(ei.value)
+    bad.close()
+    good = gc.BatchPlan("dilate", dev_items)
+    good.launch()
+    good.status()
+    check_items("dilate", items, good.outs)
