@@ -1792,8 +1792,9 @@ static int run_bwd_sources(gc_dtype dtype, const uint32_t *sources, const void *
     if (s.width == 0 || s.height == 0 || n == 0) return GC_OK;
     const int64_t span = (s.height - 1) * s.pitch + s.width;
     const int64_t istride = n > 1 ? stride : span;
-    // x: columns in groups of 256; y: rows, strided; z: images
-    const dim3 grid((unsigned)((s.width + 255) / 256), (unsigned)std::min<int64_t>(s.height, 64), (unsigned)n);
+    // x: columns in groups of 256; y: rows (one per block up to 65535, then
+    // strided); z: images
+    const dim3 grid((unsigned)((s.width + 255) / 256), (unsigned)std::min<int64_t>(s.height, 65535), (unsigned)n);
     SrcScatterArgs a{};
     a.ids = sources;
     a.g_out = g_out;

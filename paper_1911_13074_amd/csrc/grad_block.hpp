@@ -217,7 +217,10 @@ __global__ __launch_bounds__(GradTile<T>::THREADS, GradTile<T>::CODES_WAVES_PER_
                 const T right = gb_shift<DPP_WAVE_SHL1>(c);
                 const T best = extremum<OP>(extremum<OP>(left, c), right);
                 h[r] = best;
-                ix[r] = left == best ? 0 : (c == best ? 1 : 2);
+                // two unconditional selects (a nested conditional of this
+                // shape compiles to divergent branches)
+                const int t = c == best ? 1 : 2;
+                ix[r] = left == best ? 0 : t;
             }
             xv[par][w][0][x] = h[0];
             xi[par][w][0][x] = (uint8_t)ix[0];
@@ -239,7 +242,8 @@ __global__ __launch_bounds__(GradTile<T>::THREADS, GradTile<T>::CODES_WAVES_PER_
                 const T hd = r == GB_WR - 1 ? hb : h[r + 1];
                 const int id = r == GB_WR - 1 ? ib : ix[r + 1];
                 const T best = extremum<OP>(extremum<OP>(hu, h[r]), hd);
-                const int code = hu == best ? iu : (h[r] == best ? 3 + ix[r] : 6 + id);
+                const int t = h[r] == best ? 3 + ix[r] : 6 + id;
+                const int code = hu == best ? iu : t;
                 const bool mask_wins = OP == OP_DILATE ? !(best < m[r]) : !(best > m[r]);
                 v[r] = mask_wins ? m[r] : best;
                 const int cy = w * GB_WR + r - GB_K;
@@ -432,6 +436,13 @@ struct SrcBlockArgs {
     int32_t k;                // steps in this launch (<= GB_K)
 };
 
+// Selects of ids: two unconditional selects (the compiler turns a nested
+// conditional of this shape into divergent branches).
+__device__ __forceinline__ uint32_t pick_id(bool first, uint32_t a, bool second, uint32_t b, uint32_t c) {
+    const uint32_t t = second ? b : c;
+    return first ? a : t;
+}
+
 template <typename T, int OP>
 __global__ __launch_bounds__(GradTile<T>::THREADS) void block_src_kernel(SrcBlockArgs a) {
     using B = Bounds<T, OP>;
@@ -456,7 +467,7 @@ __global__ __launch_bounds__(GradTile<T>::THREADS) void block_src_kernel(SrcBloc
     const bool col_core = (unsigned)(x - GB_K) < (unsigned)GB_CX;
 
     T v[GB_WR], m[GB_WR];
-    uint32_t id[GB_WR];
+    uint32_t id[GB_WR], mid[GB_WR];
 #pragma unroll
     for (int r = 0; r < GB_WR; ++r) {
         const int y = ry0 + w * GB_WR + r;
@@ -466,6 +477,7 @@ __global__ __launch_bounds__(GradTile<T>::THREADS) void block_src_kernel(SrcBloc
         m[r] = in ? msk[off] : B::bottom();
         // outside the image: never chosen (its value never wins), any id
         id[r] = in ? (ids_in ? ids_in[off] : (uint32_t)off) : 0u;
+        mid[r] = SRC_MASK | (uint32_t)off;   // the id of this pixel's mask value
     }
 
     const int k = a.k;
@@ -485,7 +497,7 @@ __global__ __launch_bounds__(GradTile<T>::THREADS) void block_src_kernel(SrcBloc
                 const uint32_t ir = (uint32_t)gb_shift<DPP_WAVE_SHL1>((int)id[r]);
                 const T best = extremum<OP>(extremum<OP>(left, c), right);
                 h[r] = best;
-                hs[r] = left == best ? il : (c == best ? id[r] : ir);
+                hs[r] = pick_id(left == best, il, c == best, id[r], ir);
             }
             xv[par][w][0][x] = h[0];
             xs[par][w][0][x] = hs[0];
@@ -497,8 +509,8 @@ __global__ __launch_bounds__(GradTile<T>::THREADS) void block_src_kernel(SrcBloc
             const T ha = xv[par][wa][1][x], hb = xv[par][wb][0][x];
             const uint32_t sa = xs[par][wa][1][x], sb = xs[par][wb][0][x];
             // column pass (rows y-1, y, y+1 in that order), then the clamp
-            // (the mask wins ties); one register array of ids per step
-            uint32_t nid[GB_WR];
+            // (the mask wins ties); the row pass results are all read before
+            // v and id are overwritten
 #pragma unroll
             for (int r = 0; r < GB_WR; ++r) {
                 const T hu = r == 0 ? ha : h[r - 1];
@@ -506,14 +518,11 @@ __global__ __launch_bounds__(GradTile<T>::THREADS) void block_src_kernel(SrcBloc
                 const T hd = r == GB_WR - 1 ? hb : h[r + 1];
                 const uint32_t sd = r == GB_WR - 1 ? sb : hs[r + 1];
                 const T best = extremum<OP>(extremum<OP>(hu, h[r]), hd);
-                const uint32_t sb_ = hu == best ? su : (h[r] == best ? hs[r] : sd);
+                const uint32_t from = pick_id(hu == best, su, h[r] == best, hs[r], sd);
                 const bool mask_wins = OP == OP_DILATE ? !(best < m[r]) : !(best > m[r]);
-                const int64_t off = (int64_t)(ry0 + w * GB_WR + r) * a.pitch + gx;
                 v[r] = mask_wins ? m[r] : best;
-                nid[r] = mask_wins ? (SRC_MASK | (uint32_t)off) : sb_;
+                id[r] = mask_wins ? mid[r] : from;
             }
-#pragma unroll
-            for (int r = 0; r < GB_WR; ++r) id[r] = nid[r];
         }
     }
     // core of the state after the block, with its ids
