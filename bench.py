@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB, 5 times "
                          "(reference dispatch for HBM byte counters), then exit")
+    ap.add_argument("--fwd-bwd-only", action="store_true",
+                    help="only run the differentiable workload (16 x 1024^2 f32, 200 steps, source ids) "
+                         "three times and print its time, then exit (for profiling its kernels)")
     ap.add_argument("--batch-shapes", action="store_true",
                     help="only time the 64-image batch split into size classes under every launch "
                          "shape (tile family x steps per block), print one JSON line, then exit")
@@ -342,6 +345,19 @@ def main():
 
     if args.batch_shapes:
         print(json.dumps({"batch_shape_study": batch_shape_study(gc, dev)}), flush=True)
+        return
+    if args.fwd_bwd_only:
+        fd, md, gd = workloads.differentiable_f32(size=args.size)
+        Fd, Md, Gd = (torch.from_numpy(a).to(dev) for a in (fd, md, gd))
+
+        def fwd_bwd():
+            Fr = Fd.detach().requires_grad_(True)
+            Mr = Md.detach().requires_grad_(True)
+            gc.geodesic_chain(Fr, Mr, 200, op="dilate", checkpoint_every=32, method="sources").backward(Gd)
+
+        ms = timed(fwd_bwd, 3, 1)
+        print(json.dumps({"fwd_bwd_16x1024_f32_200_ms": round(ms, 3),
+                          "gpx_steps_per_s": round(Fd.numel() * 200 / ms / 1e6, 2)}), flush=True)
         return
 
     N, S = args.chain, args.size

@@ -434,8 +434,10 @@ int gc_geodesic_chain_bwd(gc_dtype dtype, gc_op op, const uint8_t *codes, const 
  * pixel).  The additions into one pixel happen in an unspecified order
  * (hardware atomics), so results can differ between calls in the last
  * bits of the sums.  grad_marker, grad_mask, grad_out and sources must not
- * overlap.  Batches as above (one launch per 8 steps, and two launches for
- * the reverse pass).
+ * overlap.  An id whose offset lies beyond the image's elements
+ * ((height - 1) * pitch + width) is ignored, so corrupted ids cannot make
+ * the pass write outside the gradient images.  Batches as above (one
+ * launch per 8 steps, and two launches for the reverse pass).
  * ------------------------------------------------------------------- */
 int gc_geodesic_chain_fwd_sources(gc_dtype dtype, gc_op op, const void *marker, const void *mask,
                                   void *out, uint32_t *sources, gc_shape shape, int32_t n_images,

@@ -1805,6 +1805,7 @@ static int run_bwd_sources(gc_dtype dtype, const uint32_t *sources, const void *
     a.width = (int32_t)s.width;
     a.height = (int32_t)s.height;
     a.n_images = n;
+    a.span = (uint32_t)span;
     if (dtype == GC_F32) {
         hipLaunchKernelGGL(src_local_kernel<float>, grid, dim3(256), 0, st, a);
         hipLaunchKernelGGL(src_scatter_kernel<float>, grid, dim3(256), 0, st, a);

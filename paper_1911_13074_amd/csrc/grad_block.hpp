@@ -546,6 +546,7 @@ struct SrcScatterArgs {
     void *g_mask;             // mask gradient, accumulated
     int64_t image_stride, pitch;
     int32_t width, height, n_images;
+    uint32_t span;            // elements of one image, (height - 1) * pitch + width
 };
 
 // The scatter in two passes.  Pass 1 (src_local_kernel) streams over the
@@ -589,10 +590,11 @@ __global__ void src_scatter_kernel(SrcScatterArgs a) {
     for (int y = blockIdx.y; y < a.height; y += gridDim.y) {
         const uint32_t pos = (uint32_t)((int64_t)y * a.pitch + x);
         const uint32_t id = ids[pos];
-        if ((id & ~SRC_MASK) == pos) continue;  // own pixel: pass 1
+        const uint32_t leaf = id & ~SRC_MASK;
+        if (leaf == pos) continue;      // own pixel: pass 1
+        if (leaf >= a.span) continue;   // not an element of the image: ignored
         const T gv = g[pos];
         if (gv == T(0)) continue;
-        const uint32_t leaf = id & ~SRC_MASK;
         unsafeAtomicAdd((id & SRC_MASK) ? gm + leaf : gf + leaf, gv);
     }
 }

@@ -283,3 +283,32 @@ def test_methods_agree_on_checkpointing():
             (gc.geodesic_chain(F, M, n, checkpoint_every=ck, method=method) * g).sum().backward()
             np.testing.assert_allclose(host(F.grad), ref_gf, rtol=1e-12, atol=1e-12 * np.abs(ref_gf).max())
             np.testing.assert_allclose(host(M.grad), ref_gm, rtol=1e-12, atol=1e-12 * np.abs(ref_gm).max())
+
+
+def test_reverse_pass_ignores_ids_beyond_the_image():
+    """Ids whose offset lies beyond the image are skipped: a source map with
+    some ids overwritten by such values gives the gradient of the valid ids
+    alone (and nothing is written outside the gradient images)."""
+    shape, n = (40, 50), 12
+    f, m = rand_pair(shape, np.float32, seed=31)
+    _, src = gc.geodesic_chain_fwd_sources("dilate", dev(f), dev(m), n)
+    bad = src.clone()
+    rng = np.random.default_rng(9)
+    ys, xs = rng.integers(0, 40, size=30), rng.integers(0, 50, size=30)
+    vals = [0x7FFFFFFF, 40 * 50, 40 * 50 + 123, -1]   # -1: the mask bit and offset 2^31 - 1
+    for i, (y, x) in enumerate(zip(ys, xs)):
+        bad[y, x] = int(np.int32(np.uint32(vals[i % 4]) if vals[i % 4] >= 0 else -1))
+    g = np.random.default_rng(10).standard_normal(shape).astype(np.float32)
+    guard = torch.full((3, 40, 50), 5.0, dtype=torch.float32, device="cuda")
+    gf, gm = guard[0], guard[1]
+    gm.zero_()
+    gc.geodesic_chain_bwd_sources(bad, dev(g), gm, grad_marker=gf)
+    # the reference: drop the contributions of the overwritten pixels
+    g_valid = g.copy()
+    g_valid[ys, xs] = 0
+    gf_ref = torch.zeros(shape, dtype=torch.float32, device="cuda")
+    gm_ref = torch.zeros(shape, dtype=torch.float32, device="cuda")
+    gc.geodesic_chain_bwd_sources(src, dev(g_valid), gm_ref, grad_marker=gf_ref)
+    np.testing.assert_allclose(host(gf), host(gf_ref), rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(host(gm), host(gm_ref), rtol=1e-6, atol=1e-6)
+    assert (host(guard[2]) == 5.0).all()
