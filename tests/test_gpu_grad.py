@@ -218,7 +218,8 @@ def sources_from_codes(codes):
 def test_sources_match_oracle_paths(dtype, op, shape, levels, n):
     """Source ids are bit-exact against the ends of the oracle's code paths
     (one launch per 8 steps, so 9, 17, 25 and 40 steps chain the ids through
-    several launches; few levels give many ties)."""
+    several launches; 130 x 200 spans several cores with ragged ends; few
+    levels give many ties)."""
     f, m = rand_pair(shape, dtype, seed=shape[0] * 7 + shape[1] + n, levels=levels)
     out, src = gc.geodesic_chain_fwd_sources(op, dev(f), dev(m), n)
     ref_out, ref_codes = oracle.chain_codes(code_of(op), f, n, m)
@@ -226,27 +227,32 @@ def test_sources_match_oracle_paths(dtype, op, shape, levels, n):
     assert np.array_equal(host(src), sources_from_codes(ref_codes))
 
 
-def test_sources_pitched_batch_and_zero_steps():
+@pytest.mark.parametrize("dtype,col0,rows,n", [(np.float64, 0, 50, 13), (np.float32, 0, 150, 21),
+                                               (np.float32, 1, 150, 21)])
+def test_sources_pitched_batch_and_zero_steps(dtype, col0, rows, n):
     """A batch of three pitched images (ids are offsets y * pitch + x within
-    each image) and a zero-step chain (every pixel its own source)."""
+    each image) and a zero-step chain (every pixel its own source), in
+    float64 and in float32, the latter also as views that start at an odd
+    column and span two rows of cores."""
     rng = np.random.default_rng(17)
-    big_f = torch.zeros((3, 50, 80), dtype=torch.float64, device="cuda")
+    big_f = torch.zeros((3, rows, 80), dtype=getattr(torch, np.dtype(dtype).name), device="cuda")
     big_m = torch.zeros_like(big_f)
-    f = rng.integers(0, 5, size=(3, 50, 70)).astype(np.float64)
-    m = rng.integers(0, 5, size=(3, 50, 70)).astype(np.float64)
-    F, M = big_f[:, :, :70], big_m[:, :, :70]
+    f = rng.integers(0, 5, size=(3, rows, 70)).astype(dtype)
+    m = rng.integers(0, 5, size=(3, rows, 70)).astype(dtype)
+    F, M = big_f[:, :, col0:col0 + 70], big_m[:, :, col0:col0 + 70]
     F.copy_(dev(f))
     M.copy_(dev(m))
-    out, src = gc.geodesic_chain_fwd_sources("dilate", F, M, 13)
+    out, src = gc.geodesic_chain_fwd_sources("dilate", F, M, n)
     s = host(src).view(np.uint32)
     for b in range(3):
-        _, codes = oracle.chain_codes(oracle.DILATE, f[b], 13, m[b])
+        ref_out, codes = oracle.chain_codes(oracle.DILATE, f[b], n, m[b])
+        assert np.array_equal(host(out)[b], ref_out), f"image {b}"
         ref = sources_from_codes(codes).view(np.uint32)
         pos = ref & 0x7FFFFFFF
         want = (pos // 70) * 80 + pos % 70 | (ref & 0x80000000)
         assert np.array_equal(s[b], want), f"image {b}"
     _, src0 = gc.geodesic_chain_fwd_sources("erode", dev(f[0]), dev(m[0]), 0)
-    assert np.array_equal(host(src0), np.arange(50 * 70, dtype=np.int32).reshape(50, 70))
+    assert np.array_equal(host(src0), np.arange(rows * 70, dtype=np.int32).reshape(rows, 70))
 
 
 @pytest.mark.parametrize("op", OPS)
