@@ -560,8 +560,9 @@ def main():
 
         px_d = Fd.numel() * 200
         # Two ways through the same gradient: source ids (the per-step
-        # routes composed over each 32-step segment, one scatter per
-        # segment; the default) and per-step codes with the reverse gather.
+        # routes composed over the whole chain in the forward, one scatter
+        # back; the default) and per-step codes with the reverse gather
+        # (checkpoints every 32 steps, each segment recomputed).
         ms_fb = timed(fwd_bwd, 3, 1)
         ms_fb_codes = timed(lambda: fwd_bwd("codes"), 3, 1)
         ms_fo = timed(fwd_only, 3, 1)
@@ -575,9 +576,9 @@ def main():
         c_ms, c_n, c_st = kernel_profile(lambda: gc.geodesic_chain_fwd_codes("dilate", Fd, Md, 32, codes=codes), 2)
         b_ms, b_n, b_st = kernel_profile(lambda: gc.geodesic_chain_bwd("dilate", codes, Gd, gm), 2)
         del codes
-        # Source ids: the recomputation of one 32-step segment carrying ids
-        # (read state, mask and ids, write state and ids: 5s per pixel and
-        # launch of up to 8 steps; the first launch reads no ids), and the
+        # Source ids: 32 steps carrying ids (read state, mask and ids, write
+        # state and ids: 5s per pixel and launch of up to 8 steps; the first
+        # launch reads no ids), and the
         # scatter (read ids and gradient, read-modify-write one leaf
         # gradient per pixel, zero the marker gradient first: about 5s).
         _, srcs = gc.geodesic_chain_fwd_sources("dilate", Fd, Md, 32)
@@ -597,7 +598,7 @@ def main():
             "gpx_steps_per_s": round(px_d / ms_fb / 1e6, 2), "ms": round(ms_fb, 3), "method": "sources",
             "forward_only_gpx_steps_per_s": round(px_d / ms_fo / 1e6, 2),
             "vs_plain": round(px_d / ms_fb / 1e6 / value, 4),
-            "vs_f32_forward": round(ms_fo / ms_fb, 4), "checkpoint_every": 32,
+            "vs_f32_forward": round(ms_fo / ms_fb, 4), "codes_checkpoint_every": 32,
             "codes_method": {"gpx_steps_per_s": round(px_d / ms_fb_codes / 1e6, 2), "ms": round(ms_fb_codes, 3)},
             "sources_kernel": {"avg_launch_ms": round(s_ms, 4), "steps_per_launch": round(k_s, 2),
                                "gpx_steps_per_s": round(npx * k_s / (s_ms * 1e-3) / 1e9, 1),

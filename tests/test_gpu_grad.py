@@ -144,6 +144,32 @@ def test_batched_images_and_zero_steps(method):
     assert np.array_equal(host(F0.grad), g) and not host(M0.grad).any()
 
 
+def test_sources_forward_without_gradients_and_mask_only():
+    """With method='sources' a forward that no backward can follow (grad
+    mode off, or inputs that need no gradient) runs the plain chain: the
+    same output, bit-exact against the oracle; with only the mask
+    requiring a gradient, the ids are kept and the mask gradient matches
+    the oracle's."""
+    f, m = rand_pair((2, 45, 70), np.float32, seed=12, levels=5)
+    g = np.random.default_rng(3).standard_normal((2, 45, 70)).astype(np.float32)
+    F = dev(f).requires_grad_(True)
+    M = dev(m).requires_grad_(True)
+    y = gc.geodesic_chain(F, M, 21)
+    with torch.no_grad():
+        y0 = gc.geodesic_chain(F, M, 21)
+    y1 = gc.geodesic_chain(dev(f), dev(m), 21)
+    assert y.requires_grad and not y0.requires_grad and not y1.requires_grad
+    for b in range(2):
+        ref = oracle.chain(oracle.DILATE, f[b], 21, m[b])
+        for out in (y, y0, y1):
+            assert np.array_equal(host(out)[b], ref), f"image {b}"
+    M2 = dev(m).requires_grad_(True)
+    (gc.geodesic_chain(dev(f), M2, 21) * dev(g)).sum().backward()
+    for b in range(2):
+        _, rm = oracle.chain_vjp(oracle.DILATE, f[b], m[b], 21, g[b])
+        np.testing.assert_allclose(host(M2.grad)[b], rm, rtol=1e-5, atol=1e-5 * max(np.abs(rm).max(), 1))
+
+
 @pytest.fixture(scope="module")
 def differentiable_workload():
     """16 x 1024 x 1024 float32, 200 geodesic dilations, upstream N(0,1),
