@@ -603,7 +603,7 @@ def main():
             "sources_kernel": {"avg_launch_ms": round(s_ms, 4), "steps_per_launch": round(k_s, 2),
                                "gpx_steps_per_s": round(npx * k_s / (s_ms * 1e-3) / 1e9, 1),
                                "hbm_gb_s": round(20 * npx / (s_ms * 1e-3) / 1e9, 1), "peak_gb_s": 8000},
-            "scatter": {"ms_per_segment": round(sc_ms, 4),
+            "scatter": {"ms_per_call": round(sc_ms, 4),
                         "hbm_gb_s": round(20 * npx / (sc_ms * 1e-3) / 1e9, 1), "peak_gb_s": 8000},
             "codes_kernel": {"avg_launch_ms": round(c_ms, 4), "steps_per_launch": round(k_c, 2),
                              "gpx_steps_per_s": round(npx * k_c / (c_ms * 1e-3) / 1e9, 1),
