@@ -1244,12 +1244,24 @@ __device__ __forceinline__ int xcd_tile(unsigned b, unsigned n) {
     return (int)(b & 7u) * (int)(n >> 3) + (int)(b >> 3);
 }
 
+// Change bits of a workgroup go out as one device-scope atomic: the waves
+// that hold any first OR them into a word in LDS (set to zero before the
+// body's first barrier).  One atomic per wave put up to eight times as
+// many atomics on the single change word, where they serialise.
+__device__ __forceinline__ void publish_change_bits(uint32_t &wg_bits, uint32_t bits, uint32_t *word) {
+    if (bits != 0 && (threadIdx.x & 63) == 0) atomicOr(&wg_bits, bits);
+    __syncthreads();
+    if (threadIdx.x == 0 && wg_bits != 0) atomicOr(word, wg_bits);
+}
+
 template <typename T, int OP, int MODE, bool DETECT, int CW, int RPW, int NW, int G = 1>
 __global__ __launch_bounds__(64 * NW) void chain_block_kernel(BlockArgs a) {
     if (DETECT && a.prev_word != nullptr) {
         // The image stopped changing in an earlier launch: nothing to do.
         if (*a.prev_word != a.prev_full) return;
     }
+    __shared__ uint32_t wg_bits;
+    if (DETECT && threadIdx.x == 0) wg_bits = 0;
     int tile = a.tile0 + xcd_tile(blockIdx.x, gridDim.x);
     BlockArgs b = a;
     if (a.tiles_per_image > 0) {
@@ -1270,9 +1282,7 @@ __global__ __launch_bounds__(64 * NW) void chain_block_kernel(BlockArgs a) {
     __shared__ __attribute__((aligned(16))) uint8_t stage[stage_bytes<T, CW, RPW, NW, G, true>()];
     const uint32_t bits =
         chain_block_dispatch<T, OP, MODE, DETECT, CW, RPW, NW, G, false, true>(b, rx0, ry0, xch, stage);
-    if constexpr (DETECT) {
-        if (bits != 0 && (threadIdx.x & 63) == 0) atomicOr(a.change_word, bits);
-    }
+    if constexpr (DETECT) publish_change_bits(wg_bits, bits, a.change_word);
 }
 
 }  // namespace geochain

@@ -110,6 +110,10 @@ __global__ __launch_bounds__(64 * NW) void persistent_chain_kernel(PersistentArg
 
     const int tid = threadIdx.x;
     __shared__ int32_t drawn;
+    // change bits of the current item, ORed by its waves (one device-scope
+    // atomic per item instead of one per wave, as in chain_block_kernel)
+    __shared__ uint32_t wg_bits;
+    if (DETECT && tid == 0) wg_bits = 0;
     for (;;) {
         // ---- draw the next chunk of items (list order) ----
         // The first wave as a whole takes this branch (a uniform condition);
@@ -178,7 +182,7 @@ __global__ __launch_bounds__(64 * NW) void persistent_chain_kernel(PersistentArg
             // what orders them before the counter.
             const uint32_t bits = chain_block_dispatch<T, OP, MODE, DETECT, CW, RPW, NW, G, true>(ba, rx0, ry0, xch, stage);
             if constexpr (DETECT) {
-                if (bits != 0 && im.change != nullptr && (tid & 63) == 0) atomicOr(im.change + b, bits);
+                if (bits != 0 && (tid & 63) == 0) atomicOr(&wg_bits, bits);
             }
 
             // ---- publish: stores first, then the tile's counter ----
@@ -187,6 +191,13 @@ __global__ __launch_bounds__(64 * NW) void persistent_chain_kernel(PersistentArg
             __syncthreads();
             if (tid < 64) {
                 if (tid == 0) {
+                    if constexpr (DETECT) {
+                        // read after the barrier; cleared before wave 0 reaches
+                        // the next item's barriers, which order it before that
+                        // item's ORs
+                        if (wg_bits != 0 && im.change != nullptr) atomicOr(im.change + b, wg_bits);
+                        wg_bits = 0;
+                    }
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                     __hip_atomic_store(a.flags + im.flag_base + item.tile, (uint32_t)(b + 1), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);

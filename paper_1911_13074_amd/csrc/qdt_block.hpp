@@ -445,6 +445,8 @@ __global__ __launch_bounds__(64 * NW) void qdt_block_kernel(QdtArgs qa) {
         // an earlier launch already saw a step without change
         if (*a.prev_word != a.prev_full) return;
     }
+    __shared__ uint32_t wg_bits;
+    if (threadIdx.x == 0) wg_bits = 0;
     const int tile = a.tile0 + xcd_tile(blockIdx.x, gridDim.x);
     const int rx0 = (tile % a.tiles_x) * a.core_x - a.halo;
     const int ry0 = (tile / a.tiles_x) * a.core_y - a.halo;
@@ -460,7 +462,7 @@ __global__ __launch_bounds__(64 * NW) void qdt_block_kernel(QdtArgs qa) {
         bits = inside ? qdt_block_body<T, PHASE, false, CW, RPW, NW>(qa, rx0, ry0, xch)
                       : qdt_block_body<T, PHASE, true, CW, RPW, NW>(qa, rx0, ry0, xch);
     }
-    if (bits != 0 && (threadIdx.x & 63) == 0) atomicOr(a.change_word, bits);
+    publish_change_bits(wg_bits, bits, a.change_word);
 }
 
 }  // namespace geochain
