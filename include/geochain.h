@@ -305,7 +305,7 @@ int gc_quasi_distance(gc_dtype dtype, const void *f, int32_t *dist, void *residu
  * past the bound the launch drains and gc_plan_status reports GC_ERR_HIP
  * (results invalid).
  * With run-to-stability items it is synchronous instead: each replay runs
- * every active image for 4 blocks of 20 steps while the kernel records, per
+ * every active image for 2 blocks of 20 steps while the kernel records, per
  * block, which steps changed a pixel; between replays the host retires the
  * images that reached a step without change (their result is then a fixed
  * point) and the others continue from their output.  Fixed-length items

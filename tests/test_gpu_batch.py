@@ -267,7 +267,7 @@ def _stability_items(dtype, rng):
     items.append((np.minimum(f, m), m, -1, True))          # in place
     seed_m = np.full((150, 260), 5, dtype)
     seed_f = np.zeros_like(seed_m)
-    seed_f[0, 0] = 5                                         # 259 steps: two replays
+    seed_f[0, 0] = 5                                         # 259 steps: seven replays
     items.append((seed_f, seed_m, -1, False))
     f, m = _serpentine(31, 64)
     items.append((f.astype(dtype), m.astype(dtype), -1, False))   # about a thousand steps
@@ -284,7 +284,7 @@ def test_plan_items_run_to_stability(op, dtype):
     plan, u8, f32 and f64: every image and every step count equals the
     oracle's (the reconstruction for n < 0, the chain otherwise), across
     replays that retire converged images and continue the others (the
-    corridor needs about a thousand steps, several replays of 80)."""
+    corridor needs about a thousand steps, many replays of 40)."""
     rng = np.random.default_rng(61)
     host_items = _stability_items(dtype, rng)
     if op == "erode":   # reconstruction by erosion: marker above the mask
