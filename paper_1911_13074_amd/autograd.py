@@ -70,7 +70,7 @@ class GeodesicChainFunction(torch.autograd.Function):
             mask, src = ctx.saved_tensors
             gm = torch.zeros_like(mask)
             g = ops.geodesic_chain_bwd_sources(src, g, gm)
-            return g, gm, None, None, None, None, None
+            return (g, gm) + (None,) * (len(ctx.needs_input_grad) - 2)
         mask, *ckpts = ctx.saved_tensors
         gm = torch.zeros_like(mask)
         starts = list(range(0, ctx.n_steps, ctx.seg))
@@ -79,7 +79,8 @@ class GeodesicChainFunction(torch.autograd.Function):
             _, codes = ops.geodesic_chain_fwd_codes(ctx.op, ckpts[i], mask, n)
             g = ops.geodesic_chain_bwd(ctx.op, codes, g, gm)
             del codes
-        return g, gm, None, None, None, None, None
+        # one entry per argument given to apply (gradients_wanted may be left out)
+        return (g, gm) + (None,) * (len(ctx.needs_input_grad) - 2)
 
 
 def geodesic_chain(marker, mask, n_steps, op="dilate", checkpoint_every=32, method="sources"):
