@@ -468,24 +468,52 @@ __global__ __launch_bounds__(GradTile<T>::THREADS) void block_src_kernel(SrcBloc
 
     T v[GB_WR], m[GB_WR];
     uint32_t id[GB_WR], mid[GB_WR];
+    // a region inside the image (most tiles) loads without per-pixel tests
+    const bool interior = rx0 >= 0 && ry0 >= 0 && rx0 + GB_RW <= a.width && ry0 + NW * GB_WR <= a.height;
+    if (interior) {
+        const int64_t off0 = (int64_t)(ry0 + w * GB_WR) * a.pitch + gx;
 #pragma unroll
-    for (int r = 0; r < GB_WR; ++r) {
-        const int y = ry0 + w * GB_WR + r;
-        const bool in = xin && (unsigned)y < (unsigned)a.height;
-        const int64_t off = (int64_t)y * a.pitch + gx;
-        v[r] = in ? src[off] : B::bottom();
-        m[r] = in ? msk[off] : B::bottom();
-        // outside the image: never chosen (its value never wins), any id
-        id[r] = in ? (ids_in ? ids_in[off] : (uint32_t)off) : 0u;
-        mid[r] = SRC_MASK | (uint32_t)off;   // the id of this pixel's mask value
+        for (int r = 0; r < GB_WR; ++r) {
+            const int64_t off = off0 + r * a.pitch;
+            v[r] = src[off];
+            m[r] = msk[off];
+            id[r] = ids_in ? ids_in[off] : (uint32_t)off;
+            mid[r] = SRC_MASK | (uint32_t)off;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < GB_WR; ++r) {
+            const int y = ry0 + w * GB_WR + r;
+            const bool in = xin && (unsigned)y < (unsigned)a.height;
+            const int64_t off = (int64_t)y * a.pitch + gx;
+            v[r] = in ? src[off] : B::bottom();
+            m[r] = in ? msk[off] : B::bottom();
+            // outside the image: never chosen (its value never wins), any id
+            id[r] = in ? (ids_in ? ids_in[off] : (uint32_t)off) : 0u;
+            mid[r] = SRC_MASK | (uint32_t)off;   // the id of this pixel's mask value
+        }
     }
 
+    // This wave's exchange slots: the parity and the edge row are compile-time
+    // offsets from these (two steps per loop iteration), so the step loop
+    // spends no VALU on LDS addresses.
+    T *const xw = &xv[0][w][0][x];
+    uint32_t *const sw = &xs[0][w][0][x];
+    const T *const xa = &xv[0][wa][1][x];
+    const T *const xb = &xv[0][wb][0][x];
+    const uint32_t *const sa_p = &xs[0][wa][1][x];
+    const uint32_t *const sb_p = &xs[0][wb][0][x];
+    constexpr int PAR_T = NW * 2 * GB_RW;   // elements between the parities
+    constexpr int ROW_T = GB_RW;            // between a wave's first and last row
+
     const int k = a.k;
-    for (int s = 0; s < k; ++s) {
-        const int par = s & 1;
+    // row-pass results of a step (kept across steps: a wave that skips a
+    // step neither writes nor reads them)
+    T h[GB_WR];
+    uint32_t hs[GB_WR];
+    auto step = [&](int s, auto par_tag) {
+        constexpr int par = decltype(par_tag)::value;
         const bool busy = gb_wave_busy<CY>(w, k, s);
-        T h[GB_WR];
-        uint32_t hs[GB_WR];
         if (busy) {
             // row pass: the first of (x-1, x, x+1) equal to their extremum
 #pragma unroll
@@ -499,15 +527,15 @@ __global__ __launch_bounds__(GradTile<T>::THREADS) void block_src_kernel(SrcBloc
                 h[r] = best;
                 hs[r] = pick_id(left == best, il, c == best, id[r], ir);
             }
-            xv[par][w][0][x] = h[0];
-            xs[par][w][0][x] = hs[0];
-            xv[par][w][1][x] = h[GB_WR - 1];
-            xs[par][w][1][x] = hs[GB_WR - 1];
+            xw[par * PAR_T] = h[0];
+            sw[par * PAR_T] = hs[0];
+            xw[par * PAR_T + ROW_T] = h[GB_WR - 1];
+            sw[par * PAR_T + ROW_T] = hs[GB_WR - 1];
         }
         __syncthreads();
         if (busy) {
-            const T ha = xv[par][wa][1][x], hb = xv[par][wb][0][x];
-            const uint32_t sa = xs[par][wa][1][x], sb = xs[par][wb][0][x];
+            const T ha = xa[par * PAR_T], hb = xb[par * PAR_T];
+            const uint32_t sa = sa_p[par * PAR_T], sb = sb_p[par * PAR_T];
             // column pass (rows y-1, y, y+1 in that order), then the clamp
             // (the mask wins ties); the row pass results are all read before
             // v and id are overwritten
@@ -524,6 +552,10 @@ __global__ __launch_bounds__(GradTile<T>::THREADS) void block_src_kernel(SrcBloc
                 id[r] = mask_wins ? mid[r] : from;
             }
         }
+    };
+    for (int s = 0; s < k; s += 2) {
+        step(s, std::integral_constant<int, 0>{});
+        if (s + 1 < k) step(s + 1, std::integral_constant<int, 1>{});
     }
     // core of the state after the block, with its ids
     if (col_core && xin) {
