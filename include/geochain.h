@@ -395,8 +395,10 @@ int gc_autotune_clear(void);
  *
  * Batches: n_images images of one shape, image i at element offset
  * i * image_stride from each image pointer (image_stride >= (height - 1) *
- * pitch + width when n_images > 1).  One kernel launch per step covers the
- * whole batch.
+ * pitch + width when n_images > 1; n_images <= 65535).  Each launch (up to
+ * 8 steps) covers the whole batch.  Images of more than 65535 * 112 rows
+ * (f32) or 65535 * 80 rows (f64) return GC_ERR_UNSUPPORTED, for this call
+ * and the source-id calls below.
  * ------------------------------------------------------------------- */
 int gc_geodesic_chain_fwd_codes(gc_dtype dtype, gc_op op, const void *marker, const void *mask,
                                 void *out, uint8_t *codes, gc_shape shape, int32_t n_images,

@@ -1596,6 +1596,10 @@ static int validate_batch(gc_dtype dtype, const gc_shape &s, int32_t n_images, i
     if (n_images < 0) return fail(GC_ERR_INVALID_ARG, "n_images < 0");
     if (n_steps < 0) return fail(GC_ERR_INVALID_ARG, "n_steps < 0");
     if (n_images > 65535) return fail(GC_ERR_UNSUPPORTED, "at most 65535 images per call");
+    // the gradient kernels take one row of workgroups per core height
+    const int64_t cy = dtype == GC_F32 ? GradTile<float>::CY : GradTile<double>::CY;
+    if ((s.height + cy - 1) / cy > 65535)
+        return fail(GC_ERR_UNSUPPORTED, "gradients take images of at most %lld rows", (long long)(65535 * cy));
     const int64_t span = s.height > 0 ? (s.height - 1) * s.pitch + s.width : 0;
     if (n_images > 1 && image_stride < span)
         return fail(GC_ERR_INVALID_ARG, "image_stride %lld < image span %lld", (long long)image_stride,

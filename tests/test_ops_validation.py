@@ -98,8 +98,9 @@ def test_source_wrappers_refuse_mismatched_layouts(make, msg):
 
 
 def test_source_entry_points_validate_on_the_host():
-    """Null pointers, unknown op, integer dtype and images beyond 2^31 - 1
-    elements are refused before any HIP call."""
+    """Null pointers, unknown op, integer dtype, images beyond 2^31 - 1
+    elements and images taller than the kernels' grid are refused before any
+    HIP call."""
     FAKE = 1 << 40
     far = 1 << 44
     s = abi.gc_shape(9, 8, 9)
@@ -113,6 +114,11 @@ def test_source_entry_points_validate_on_the_host():
     assert abi.gc_geodesic_chain_fwd_sources(abi.GC_F32, abi.GC_DILATE, FAKE, FAKE + far, FAKE + 2 * far,
                                              FAKE + 3 * far, big, 1, 0, 3, None) == abi.GC_ERR_UNSUPPORTED
     assert "2^31" in abi.last_error()
+    # one row of workgroups per core height: 65535 * 112 rows in float32
+    tall = abi.gc_shape(16, 65535 * 112 + 1, 16)
+    assert abi.gc_geodesic_chain_fwd_sources(abi.GC_F32, abi.GC_DILATE, FAKE, FAKE + far, FAKE + 2 * far,
+                                             FAKE + 3 * far, tall, 1, 0, 3, None) == abi.GC_ERR_UNSUPPORTED
+    assert "rows" in abi.last_error()
     assert abi.gc_geodesic_chain_bwd_sources(abi.GC_F64, FAKE, FAKE + far, FAKE + far, FAKE + 2 * far,
                                              s, 1, 0, None) == abi.GC_ERR_ALIAS
     assert abi.gc_geodesic_chain_bwd_sources(abi.GC_F64, None, FAKE + far, FAKE + 2 * far, FAKE + 3 * far,
