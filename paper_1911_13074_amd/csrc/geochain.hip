@@ -1269,7 +1269,7 @@ static PlanChoice choose_plan_batch(gc_dtype d, int op, int mode, const std::vec
         }
     }
     if (forced_fam >= 0) c.fam = forced_fam;
-    if (const char *e = getenv("GC_PLAN_WGS_PER_CU")) c.wgs_per_cu = atoi(e);
+    if (const char *e = getenv("GEOCHAIN_PLAN_WGS_PER_CU")) c.wgs_per_cu = atoi(e);   // a measurement override
     for (size_t i = 0; i < items.size(); ++i) {
         int k = default_persistent_k(c.fam);
         if (all_tuned && vals[i].k[c.fam] > 0) k = vals[i].k[c.fam];
