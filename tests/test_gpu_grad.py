@@ -240,12 +240,13 @@ def sources_from_codes(codes):
 @pytest.mark.parametrize("op", OPS)
 @pytest.mark.parametrize("shape,levels,n", [((1, 1), None, 3), ((1, 70), 3, 9), ((33, 1), 3, 17),
                                             ((37, 129), 4, 9), ((70, 65), None, 8), ((130, 200), 6, 25),
-                                            ((61, 97), 2, 40)])
+                                            ((61, 97), 2, 40), ((300, 260), 5, 21)])
 def test_sources_match_oracle_paths(dtype, op, shape, levels, n):
     """Source ids are bit-exact against the ends of the oracle's code paths
     (one launch per 8 steps, so 9, 17, 25 and 40 steps chain the ids through
-    several launches; 130 x 200 spans several cores with ragged ends; few
-    levels give many ties)."""
+    several launches; 130 x 200 spans several cores with ragged ends, and
+    300 x 260 has tiles whose whole region lies inside the image, which load
+    without per-pixel tests; few levels give many ties)."""
     f, m = rand_pair(shape, dtype, seed=shape[0] * 7 + shape[1] + n, levels=levels)
     out, src = gc.geodesic_chain_fwd_sources(op, dev(f), dev(m), n)
     ref_out, ref_codes = oracle.chain_codes(code_of(op), f, n, m)
