@@ -356,8 +356,10 @@ int gc_plan_tune(gc_plan *plan, double *best_ms);
 /* ---------------------------------------------------------------------
  * Autotuner.  Times every candidate (tile family x steps per block) of the
  * persistent kernel on scratch images of the given size class and records
- * the fastest in a process-wide table that gc_plan_create and the
- * single-image chains consult.  Size class = (ceil(log2 width),
+ * the fastest in a process-wide table that gc_plan_create consults (a plan
+ * whose items all have entries takes the tile family with the least
+ * predicted time and each item's steps per block for it; single-image
+ * chains keep their own launch shapes).  Size class = (ceil(log2 width),
  * ceil(log2 height)).  geodesic != 0 tunes the geodesic kernel, else the
  * plain one.  Synchronises the device; allocates scratch memory.
  * best_tile / best_k (may be NULL) receive the choice.
@@ -367,6 +369,36 @@ int gc_autotune(gc_dtype dtype, gc_op op, int32_t geodesic, int64_t width, int64
 
 /* Drop every autotuner entry. */
 int gc_autotune_clear(void);
+
+/* ---------------------------------------------------------------------
+ * The autotuner's table as plain records, so that a later process can
+ * reuse the timings instead of tuning again (the Python layer keeps them
+ * in a JSON file: autotune_save / autotune_load).  One record per size
+ * class: dtype, op, geodesic (0/1), the class (sides up to 2^log2_width x
+ * 2^log2_height, log2 in 0..14), the chosen tile family, and per family
+ * the steps per block and the measured rate in pixel-steps per second
+ * (0 where a family was not timed).  Host memory, caller-owned; neither
+ * call touches the GPU.
+ *
+ * gc_autotune_export copies at most cap records into out (out may be NULL
+ * when cap is 0) and sets *count to the number the table holds.
+ * gc_autotune_import adds the records, replacing those of the same class;
+ * it checks them all first (known dtype, op and family; geodesic 0 or 1;
+ * log2 sides in 0..14; steps per block in 0..63 with the chosen family's
+ * at least 1; rates finite and >= 0) and on any bad record returns
+ * GC_ERR_INVALID_ARG with the table unchanged.
+ * ------------------------------------------------------------------- */
+#define GC_TUNE_FAMILIES 5
+typedef struct {
+    int32_t dtype, op, geodesic;
+    int32_t log2_width, log2_height;
+    int32_t best_tile;
+    int32_t k[GC_TUNE_FAMILIES];
+    double rate[GC_TUNE_FAMILIES];
+} gc_tune_entry;
+
+int gc_autotune_export(gc_tune_entry *out, int32_t cap, int32_t *count);
+int gc_autotune_import(const gc_tune_entry *entries, int32_t n);
 
 /* ---------------------------------------------------------------------
  * Differentiation of a geodesic chain (not in the paper).  f32 and f64

@@ -12,6 +12,9 @@ from .ops import (  # noqa: F401
     asf,
     autotune,
     autotune_clear,
+    autotune_load,
+    autotune_records,
+    autotune_save,
     dilate_chain,
     dome,
     erode_chain,

@@ -33,6 +33,15 @@ class gc_item(ctypes.Structure):
                 ("shape", gc_shape), ("n_steps", ctypes.c_int64)]
 
 
+GC_TUNE_FAMILIES = 5
+
+
+class gc_tune_entry(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("op", ctypes.c_int32), ("geodesic", ctypes.c_int32),
+                ("log2_width", ctypes.c_int32), ("log2_height", ctypes.c_int32), ("best_tile", ctypes.c_int32),
+                ("k", ctypes.c_int32 * GC_TUNE_FAMILIES), ("rate", ctypes.c_double * GC_TUNE_FAMILIES)]
+
+
 class GeochainError(RuntimeError):
     def __init__(self, status, func, detail):
         self.status = status
@@ -82,6 +91,8 @@ SIGNATURES = {
     "gc_autotune": (ctypes.c_int, [_DT, _DT, _I32, _I64, _I64, ctypes.POINTER(_I32),
                                    ctypes.POINTER(_I32)]),
     "gc_autotune_clear": (ctypes.c_int, []),
+    "gc_autotune_export": (ctypes.c_int, [ctypes.POINTER(gc_tune_entry), _I32, ctypes.POINTER(_I32)]),
+    "gc_autotune_import": (ctypes.c_int, [ctypes.POINTER(gc_tune_entry), _I32]),
     "gc_geodesic_chain_fwd_codes": (ctypes.c_int, [_DT, _DT, _VP, _VP, _VP, _VP, gc_shape, _I32, _I64,
                                                    _I64, _VP]),
     "gc_geodesic_chain_bwd": (ctypes.c_int, [_DT, _DT, _VP, _VP, _VP, _VP, gc_shape, _I32, _I64, _I64, _VP]),

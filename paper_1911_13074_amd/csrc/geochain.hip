@@ -2475,6 +2475,70 @@ int gc_autotune_clear(void) {
     return GC_OK;
 }
 
+static_assert(GC_TUNE_FAMILIES == NUM_FAMS, "one tuning record slot per tile family");
+
+int gc_autotune_export(gc_tune_entry *out, int32_t cap, int32_t *count) {
+    g_last_error.clear();
+    if (!count) return fail(GC_ERR_INVALID_ARG, "count is NULL");
+    if (cap < 0) return fail(GC_ERR_INVALID_ARG, "cap < 0");
+    if (cap > 0 && !out) return fail(GC_ERR_INVALID_ARG, "out is NULL");
+    std::lock_guard<std::mutex> g(g_autotune_mu);
+    int32_t i = 0;
+    for (const auto &kv : g_autotune) {
+        if (i >= cap) break;
+        gc_tune_entry e{};
+        e.dtype = kv.first.dtype;
+        e.op = kv.first.op;
+        e.geodesic = kv.first.geodesic;
+        e.log2_width = kv.first.cw;
+        e.log2_height = kv.first.ch;
+        e.best_tile = kv.second.best_fam;
+        for (int f = 0; f < NUM_FAMS; ++f) {
+            e.k[f] = kv.second.k[f];
+            e.rate[f] = kv.second.rate[f];
+        }
+        out[i++] = e;
+    }
+    *count = (int32_t)g_autotune.size();
+    return GC_OK;
+}
+
+int gc_autotune_import(const gc_tune_entry *entries, int32_t n) {
+    g_last_error.clear();
+    if (n < 0) return fail(GC_ERR_INVALID_ARG, "n < 0");
+    if (n > 0 && !entries) return fail(GC_ERR_INVALID_ARG, "entries is NULL");
+    for (int32_t i = 0; i < n; ++i) {
+        const gc_tune_entry &e = entries[i];
+        if (e.dtype != GC_U8 && e.dtype != GC_F32 && e.dtype != GC_F64)
+            return fail(GC_ERR_INVALID_ARG, "record %d: unknown dtype %d", i, e.dtype);
+        if (e.op != GC_DILATE && e.op != GC_ERODE) return fail(GC_ERR_INVALID_ARG, "record %d: unknown op %d", i, e.op);
+        if (e.geodesic != 0 && e.geodesic != 1)
+            return fail(GC_ERR_INVALID_ARG, "record %d: geodesic must be 0 or 1", i);
+        if (e.log2_width < 0 || e.log2_width > 14 || e.log2_height < 0 || e.log2_height > 14)
+            return fail(GC_ERR_INVALID_ARG, "record %d: size class outside 2^0..2^14", i);
+        if (e.best_tile < 0 || e.best_tile >= NUM_FAMS)
+            return fail(GC_ERR_INVALID_ARG, "record %d: unknown tile family %d", i, e.best_tile);
+        for (int f = 0; f < NUM_FAMS; ++f) {
+            if (e.k[f] < 0 || e.k[f] > 63) return fail(GC_ERR_INVALID_ARG, "record %d: steps per block outside 0..63", i);
+            if (!(e.rate[f] >= 0.0) || !std::isfinite(e.rate[f]))
+                return fail(GC_ERR_INVALID_ARG, "record %d: rates must be finite and >= 0", i);
+        }
+        if (e.k[e.best_tile] < 1) return fail(GC_ERR_INVALID_ARG, "record %d: the chosen family has no steps per block", i);
+    }
+    std::lock_guard<std::mutex> g(g_autotune_mu);
+    for (int32_t i = 0; i < n; ++i) {
+        const gc_tune_entry &e = entries[i];
+        TuneVal tv;
+        tv.best_fam = e.best_tile;
+        for (int f = 0; f < NUM_FAMS; ++f) {
+            tv.k[f] = e.k[f];
+            tv.rate[f] = e.rate[f];
+        }
+        g_autotune[TuneKey{e.dtype, e.op, e.geodesic, e.log2_width, e.log2_height}] = tv;
+    }
+    return GC_OK;
+}
+
 int gc_profile_enable(int on) {
     std::lock_guard<std::mutex> g(g_prof_mu);
     g_prof_on = on != 0;

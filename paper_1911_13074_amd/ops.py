@@ -8,6 +8,7 @@ Images are 2-D device tensors of dtype uint8, float32 or float64 whose rows
 are contiguous (stride(1) == 1); stride(0) is the row pitch.
 """
 import ctypes
+import json
 
 import torch
 
@@ -369,6 +370,58 @@ def autotune(dtype, op, geodesic, width, height):
 
 def autotune_clear():
     abi.check(abi.gc_autotune_clear(), "gc_autotune_clear")
+
+
+_TUNE_FORMAT = "geochain-autotune"
+_TUNE_FIELDS = ("dtype", "op", "geodesic", "log2_width", "log2_height", "best_tile")
+
+
+def autotune_records():
+    """The autotuner's table as a list of dicts (one per size class)."""
+    count = ctypes.c_int32()
+    abi.check(abi.gc_autotune_export(None, 0, ctypes.byref(count)), "gc_autotune_export")
+    n = count.value
+    arr = (abi.gc_tune_entry * max(n, 1))()
+    abi.check(abi.gc_autotune_export(arr, n, ctypes.byref(count)), "gc_autotune_export")
+    return [dict({f: getattr(e, f) for f in _TUNE_FIELDS}, k=list(e.k), rate=list(e.rate))
+            for e in arr[:min(n, count.value)]]
+
+
+def autotune_save(path):
+    """Write the autotuner's table to a JSON file, for autotune_load in a
+    later process."""
+    doc = {"format": _TUNE_FORMAT, "version": 1, "families": abi.GC_TUNE_FAMILIES,
+           "records": autotune_records()}
+    with open(path, "w") as fh:
+        json.dump(doc, fh, indent=1)
+
+
+def autotune_load(path):
+    """Add the records of a file that autotune_save wrote to the table
+    (replacing those of the same size class).  Raises ValueError for a file
+    of another shape; the library checks every value and, on a bad one,
+    leaves the table unchanged."""
+    with open(path) as fh:
+        doc = json.load(fh)
+    if not isinstance(doc, dict) or doc.get("format") != _TUNE_FORMAT or doc.get("version") != 1:
+        raise ValueError(f"{path}: not an autotune file of this library")
+    if doc.get("families") != abi.GC_TUNE_FAMILIES or not isinstance(doc.get("records"), list):
+        raise ValueError(f"{path}: records for {doc.get('families')} tile families, this build has "
+                         f"{abi.GC_TUNE_FAMILIES}")
+    recs = doc["records"]
+    arr = (abi.gc_tune_entry * max(len(recs), 1))()
+    for i, r in enumerate(recs):
+        try:
+            for f in _TUNE_FIELDS:
+                setattr(arr[i], f, int(r[f]))
+            if len(r["k"]) != abi.GC_TUNE_FAMILIES or len(r["rate"]) != abi.GC_TUNE_FAMILIES:
+                raise ValueError("one value per tile family")
+            for j in range(abi.GC_TUNE_FAMILIES):
+                arr[i].k[j] = int(r["k"][j])
+                arr[i].rate[j] = float(r["rate"][j])
+        except (KeyError, TypeError, ValueError) as exc:
+            raise ValueError(f"{path}: record {i}: {exc}") from None
+    abi.check(abi.gc_autotune_import(arr, len(recs)), "gc_autotune_import")
 
 
 def _batch_view(t: torch.Tensor, name: str):

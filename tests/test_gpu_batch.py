@@ -4,6 +4,8 @@ chain lengths, in-place items, zero-step and empty items, both tile
 families, autotuned plans, an image beyond one launch grid, and items that
 run to stability (images and step counts against the oracle's
 reconstruction)."""
+import json
+
 import numpy as np
 import pytest
 import torch
@@ -137,6 +139,30 @@ def test_autotuned_plan():
     plan.launch()
     plan.status()
     check_items("dilate", items, plan.outs)
+
+
+def test_imported_tuning_table_steers_the_plan(tmp_path):
+    """A table loaded from a file decides a plan like one the autotuner
+    filled: records for the items' size class that make tile family 0 the
+    fastest, with 24 steps per block, give a plan of that family and block
+    length, and its results stay bit-exact."""
+    rec = {"dtype": abi.GC_U8, "op": abi.GC_DILATE, "geodesic": 1, "log2_width": 9, "log2_height": 9,
+           "best_tile": 0, "k": [24, 16, 20, 16, 16], "rate": [9e12, 1e12, 1e12, 1e12, 1e12]}
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"format": "geochain-autotune", "version": 1,
+                                "families": abi.GC_TUNE_FAMILIES, "records": [rec]}))
+    gc.autotune_clear()
+    gc.autotune_load(path)
+    try:
+        items = make_batch(np.uint8, seed=23, count=6, lo=257, hi=512, n_lo=30, n_hi=90)
+        plan = gc.BatchPlan("dilate", [(dev(f), dev(m), n) for f, m, n in items])
+        info = plan.info()
+        assert info["tile"] == 0 and info["block_steps"] == 24, info
+        plan.launch()
+        plan.status()
+        check_items("dilate", items, plan.outs)
+    finally:
+        gc.autotune_clear()
 
 
 def test_mixed_plan_rejected():

@@ -21,7 +21,8 @@ CSRC = os.path.join(ROOT, "paper_1911_13074_amd", "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ASAN_RT = "/opt/rocm/llvm/lib/clang/22/lib/linux/libclang_rt.asan-x86_64.so"
-HOST_TESTS = ["tests/test_abi.py", "tests/test_ops_validation.py", "tests/test_fault_injection.py"]
+HOST_TESTS = ["tests/test_abi.py", "tests/test_ops_validation.py", "tests/test_fault_injection.py",
+              "tests/test_tune_cache.py"]
 
 
 def sources_key():
