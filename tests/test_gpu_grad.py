@@ -302,6 +302,31 @@ def test_reverse_pass_through_sources(op, dtype, levels):
     np.testing.assert_allclose(host(gm) - prior, ref_gm, rtol=tol, atol=tol * max(np.abs(ref_gm).max(), 1))
 
 
+@pytest.mark.parametrize("case", range(24))
+def test_sources_random_configurations(case):
+    """Seeded random sweep of the source-id path: dtype, op, shape (1 to 400
+    per side, so one to several tiles, interior ones included), steps (1 to
+    70, one to nine launches) and value levels; the forward bit-exact, the
+    reverse pass against the oracle's scatter."""
+    rng = np.random.default_rng(7000 + case)
+    dtype = [np.float32, np.float64][int(rng.integers(0, 2))]
+    op = OPS[int(rng.integers(0, 2))]
+    h, w = int(rng.integers(1, 401)), int(rng.integers(1, 401))
+    n = int(rng.choice([1, 2, int(rng.integers(3, 17)), int(rng.integers(17, 71))]))
+    f, m = rand_pair((h, w), dtype, seed=case, levels=int(rng.choice([2, 6, 50])))
+    g = rng.standard_normal((h, w)).astype(dtype)
+    what = f"case {case}: {np.dtype(dtype)} {op} {h}x{w} n={n}"
+    out, src = gc.geodesic_chain_fwd_sources(op, dev(f), dev(m), n)
+    ref_out, _ = oracle.chain_codes(code_of(op), f, n, m)
+    assert np.array_equal(host(out), ref_out), what
+    gm = torch.zeros((h, w), dtype=out.dtype, device="cuda")
+    gf = gc.geodesic_chain_bwd_sources(src, dev(g), gm)
+    rgf, rgm = oracle.chain_vjp(code_of(op), f, m, n, g)
+    tol = 1e-12 if dtype == np.float64 else 1e-5
+    np.testing.assert_allclose(host(gf), rgf, rtol=tol, atol=tol * max(np.abs(rgf).max(), 1), err_msg=what)
+    np.testing.assert_allclose(host(gm), rgm, rtol=tol, atol=tol * max(np.abs(rgm).max(), 1), err_msg=what)
+
+
 def test_methods_agree_on_checkpointing():
     """Both methods, several checkpoint spacings, one float64 chain: the
     gradients agree with the oracle's to 1e-12."""
