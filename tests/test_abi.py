@@ -247,3 +247,34 @@ def test_batch_chain_refusals():
     # empty batches succeed without touching the device
     assert abi.gc_geodesic_chain_batch(abi.GC_U8, abi.GC_DILATE, None, None, None, s, 0, 0, 3,
                                        None) == abi.GC_OK
+
+
+def test_struct_layouts_match_the_c_header(tmp_path):
+    """The ctypes records have the size and field offsets that a C compiler
+    gives the header's structs (compiled with gcc against include/geochain.h,
+    which must also be valid C)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    structs = {"gc_shape": abi.gc_shape, "gc_item": abi.gc_item, "gc_tune_entry": abi.gc_tune_entry}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "geochain.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'    printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'    printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        name, key, value = line.split()
+        got[(name, key)] = int(value)
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)
