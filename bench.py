@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB, 5 times "
                          "(reference dispatch for HBM byte counters), then exit")
+    ap.add_argument("--reconstruction-only", action="store_true",
+                    help="time 20 synchronous 1024^2 u8 reconstructions by dilation (for kernel traces)")
     ap.add_argument("--fwd-bwd-only", action="store_true",
                     help="only run the differentiable workload (16 x 1024^2 f32, 200 steps, source ids) "
                          "three times and print its time, then exit (for profiling its kernels)")
@@ -345,6 +347,18 @@ def main():
 
     if args.batch_shapes:
         print(json.dumps({"batch_shape_study": batch_shape_study(gc, dev)}), flush=True)
+        return
+    if args.reconstruction_only:
+        f, m = workloads.headline_u8_dilation(size=args.size)
+        F, M = torch.from_numpy(f).to(dev), torch.from_numpy(m).to(dev)
+        out = torch.empty_like(F)
+        for _ in range(3):
+            gc.reconstruct_by_dilation(F, M, out=out)
+        t0 = time.perf_counter()
+        for _ in range(20):
+            _, steps, _ = gc.reconstruct_by_dilation(F, M, out=out)
+        ms = (time.perf_counter() - t0) / 20 * 1e3
+        print(json.dumps({"reconstruction_1024_u8_ms": round(ms, 4), "steps_changed": steps}), flush=True)
         return
     if args.fwd_bwd_only:
         fd, md, gd = workloads.differentiable_f32(size=args.size)
