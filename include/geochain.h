@@ -358,8 +358,9 @@ int gc_plan_tune(gc_plan *plan, double *best_ms);
  * persistent kernel on scratch images of the given size class and records
  * the fastest in a process-wide table that gc_plan_create consults (a plan
  * whose items all have entries takes the tile family with the least
- * predicted time and each item's steps per block for it; single-image
- * chains keep their own launch shapes).  Size class = (ceil(log2 width),
+ * predicted time and each item's steps per block for it; plans with
+ * run-to-stability items and single-image chains keep their own launch
+ * shapes).  Size class = (ceil(log2 width),
  * ceil(log2 height)).  geodesic != 0 tunes the geodesic kernel, else the
  * plain one.  Synchronises the device; allocates scratch memory.
  * best_tile / best_k (may be NULL) receive the choice.

@@ -165,6 +165,40 @@ def test_imported_tuning_table_steers_the_plan(tmp_path):
         gc.autotune_clear()
 
 
+def test_stability_plan_keeps_its_shape_under_a_tuning_table(tmp_path):
+    """A plan whose items run to stability keeps the built-in launch shape
+    (128x128 regions, 20 steps per block: one change word per block) even
+    where the table names another family, and its reconstructions match the
+    oracle's, step counts included."""
+    rec = {"dtype": abi.GC_U8, "op": abi.GC_DILATE, "geodesic": 1, "log2_width": 9, "log2_height": 9,
+           "best_tile": 0, "k": [24, 16, 20, 16, 16], "rate": [9e12, 1e12, 1e12, 1e12, 1e12]}
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"format": "geochain-autotune", "version": 1,
+                                "families": abi.GC_TUNE_FAMILIES, "records": [rec]}))
+    gc.autotune_clear()
+    gc.autotune_load(path)
+    try:
+        rng = np.random.default_rng(29)
+        items = []
+        for _ in range(4):
+            h, w = int(rng.integers(257, 513)), int(rng.integers(257, 513))
+            m = rand_img((h, w), np.uint8, rng)
+            items.append((np.minimum(rand_img((h, w), np.uint8, rng), m), m))
+        plan = gc.BatchPlan("dilate", [(dev(f), dev(m), -1) for f, m in items])
+        info = plan.info()
+        assert info["tile"] == 2 and info["block_steps"] == 20, info
+        plan.launch()
+        plan.status()
+        steps = plan.steps()
+        for i, ((f, m), o) in enumerate(zip(items, plan.outs)):
+            ref, n, conv = oracle.reconstruct(oracle.DILATE, f, m)
+            assert conv and steps[i] == n, (i, steps[i], n)
+            assert np.array_equal(host(o), ref), i
+        plan.close()
+    finally:
+        gc.autotune_clear()
+
+
 def test_mixed_plan_rejected():
     a = torch.zeros((10, 10), dtype=torch.uint8, device="cuda")
     with pytest.raises(abi.GeochainError) as ei:
