@@ -853,23 +853,26 @@ static int run_operator_t(gc_dtype dtype, int which, const T *f, T *out, const g
 // ---------------------------------------------------------------------------
 // G[s] = sum of gamma_s(f), s = 0..s_max.  The erosions are kept incremental
 // (eps_s = eps_1(eps_{s-1}), the s-fold composition of Eq. 16), the
-// dilations of each opening start from eps_s.
+// dilations of each opening start from eps_s.  Each opening leaves its
+// workgroup partials in a slot of its own; one launch per SUMS_PER_LAUNCH
+// openings adds the slots' partials (then the slots are reused).
 template <typename T>
 static int run_granulometry_t(gc_dtype dtype, const T *f, const gc_shape &s, int s_max, double *G,
                               void *stream) {
     hipStream_t st = (hipStream_t)stream;
     const size_t npx = (size_t)((s.height - 1) * s.pitch + s.width);
     const size_t ext = (npx * sizeof(T) + 255) & ~(size_t)255;
+    const size_t n_sums = (size_t)s_max + 1;
+    const size_t sums_bytes = (n_sums * sizeof(double) + 255) & ~(size_t)255;
     void *b2 = nullptr;
-    int rc = get_buf2(stream, 3 * ext + (size_t)(s_max + 1) * sizeof(double), &b2);
-    if (rc != GC_OK) return rc;
-    void *partials = nullptr;
-    rc = get_partials(stream, &partials);
+    int rc = get_buf2(stream, 3 * ext + sums_bytes + (size_t)SUMS_PER_LAUNCH * PARTIALS_MAX * sizeof(double), &b2);
     if (rc != GC_OK) return rc;
     char *base = static_cast<char *>(b2);
     T *opened = reinterpret_cast<T *>(base);
     T *eroded[2] = {reinterpret_cast<T *>(base + ext), reinterpret_cast<T *>(base + 2 * ext)};
     double *sums = reinterpret_cast<double *>(base + 3 * ext);
+    double *partials = reinterpret_cast<double *>(base + 3 * ext + sums_bytes);
+    PartialCounts counts{};
     const T *eps = f;
     for (int sz = 0; sz <= s_max; ++sz) {
         const T *img = f;
@@ -885,12 +888,16 @@ static int run_granulometry_t(gc_dtype dtype, const T *f, const gc_shape &s, int
         const bool vec = rows_aligned16(s, sizeof(T), img, img);
         const PixelArgs<T> p = pixel_args<T>(s, img, nullptr, nullptr, vec);
         const int grid = px_grid(p.n_chunks, PARTIALS_MAX);
+        const int b = sz % SUMS_PER_LAUNCH;
+        double *slot = partials + (size_t)b * PARTIALS_MAX;
         if (vec)
-            hipLaunchKernelGGL((sum_kernel<T, true>), dim3(grid), dim3(PX_THREADS), 0, st, p, (double *)partials);
+            hipLaunchKernelGGL((sum_kernel<T, true>), dim3(grid), dim3(PX_THREADS), 0, st, p, slot);
         else
-            hipLaunchKernelGGL((sum_kernel<T, false>), dim3(grid), dim3(PX_THREADS), 0, st, p, (double *)partials);
-        hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(PX_THREADS), 0, st, (const double *)partials, grid,
-                           sums + sz);
+            hipLaunchKernelGGL((sum_kernel<T, false>), dim3(grid), dim3(PX_THREADS), 0, st, p, slot);
+        counts.n[b] = grid;
+        if (b == SUMS_PER_LAUNCH - 1 || sz == s_max)
+            hipLaunchKernelGGL(sum_partials_kernel, dim3(b + 1), dim3(PX_THREADS), 0, st, (const double *)partials,
+                               (int64_t)PARTIALS_MAX, counts, sums + (sz - b));
         GC_HIP(hipGetLastError());
     }
     std::vector<double> host(s_max + 1);

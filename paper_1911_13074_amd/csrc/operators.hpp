@@ -162,7 +162,8 @@ __global__ __launch_bounds__(PX_THREADS) void pixel_kernel(PixelArgs<T> p) {
 // Sum of an image (granulometric function, Eq. 17) in float64, in a fixed
 // order: each thread adds its chunks in turn, each workgroup reduces by a
 // fixed tree into one partial, and sum_partials_kernel adds those
-// partials in a fixed tree as well, so repeated calls give identical bits.
+// partials in a fixed tree as well (the partials of several images at once,
+// one workgroup each), so repeated calls give identical bits.
 // Integer-valued images sum exactly (below 2^53).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double block_sum(double v) {
@@ -197,12 +198,19 @@ __global__ __launch_bounds__(PX_THREADS) void sum_kernel(PixelArgs<T> p, double 
     if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
 
-// One workgroup: out[0] = sum of partials[0 .. n).
-__global__ __launch_bounds__(PX_THREADS) void sum_partials_kernel(const double *partials, int n, double *out) {
+// Workgroup b: out[b] = sum of partials[b * stride .. b * stride + n[b]).
+constexpr int SUMS_PER_LAUNCH = 64;
+struct PartialCounts {
+    int n[SUMS_PER_LAUNCH];
+};
+__global__ __launch_bounds__(PX_THREADS) void sum_partials_kernel(const double *partials, int64_t stride,
+                                                                  PartialCounts counts, double *out) {
+    const double *p = partials + blockIdx.x * stride;
+    const int n = counts.n[blockIdx.x];
     double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += PX_THREADS) acc += partials[i];
+    for (int i = threadIdx.x; i < n; i += PX_THREADS) acc += p[i];
     acc = block_sum(acc);
-    if (threadIdx.x == 0) out[0] = acc;
+    if (threadIdx.x == 0) out[blockIdx.x] = acc;
 }
 
 // ---------------------------------------------------------------------------

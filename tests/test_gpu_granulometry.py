@@ -51,7 +51,9 @@ def test_granulometry_parity(dtype, shape):
     check_granulometry(image(shape, dtype, seed=shape[0] + 3 * shape[1]), 6, f"{shape}")
 
 
-@pytest.mark.parametrize("s_max", [0, 1, 40])
+# 63, 64 and 130 cross the batches in which the per-size sums are added
+# (64 sizes per launch)
+@pytest.mark.parametrize("s_max", [0, 1, 40, 63, 64, 130])
 def test_granulometry_sizes(s_max):
     check_granulometry(image((90, 130), np.uint8, seed=s_max), s_max, f"s_max={s_max}")
 
