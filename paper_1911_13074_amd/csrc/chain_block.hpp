@@ -52,6 +52,8 @@ enum : int { OP_DILATE = 0, OP_ERODE = 1 };
 enum : int {
     MODE_GEODESIC = 0,   // mask read from memory (Eq. 3)
     MODE_PLAIN = 1,      // no mask (Eq. 1-2); the clamp only fences the border
+    MODE_MIXED = 2,      // as MODE_PLAIN, each step a dilation or an erosion
+                         // (BlockArgs::erode_bits; packed u8 body only)
 };
 
 template <typename T> struct RegOf;
@@ -170,6 +172,7 @@ struct BlockArgs {
     uint32_t *change_word;       // reconstruction: OR of per-step change bits
     const uint32_t *prev_word;   // reconstruction: predecessor's word (or null)
     uint32_t prev_full;          // value prev_word holds if every step changed
+    uint64_t erode_bits;         // MODE_MIXED: bit s set = step s of the launch erodes
 };
 
 // One workgroup = one tile.  CLAMP=false is the plain-chain body for regions
@@ -774,10 +777,16 @@ template <int OP, int MODE, bool CLAMP, bool DETECT, int RPW, int NW, bool AGENT
 __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int rx0, int ry0,
                                                         uint32_t (*xch)[NW][2][128], uint8_t *stage) {
     static_assert(RPW % 2 == 0, "two rows per register");
+    static_assert(MODE != MODE_MIXED || OP == OP_DILATE, "mixed chains hold the dilation form of the fence");
     constexpr int H = RPW / 2;      // registers per column
     constexpr int CW = 2;
     using B = Bounds<uint32_t, OP>;
     using P = PackedPick<OP>;
+    // State outside the image starts at the neutral value of the first
+    // step's op: for mixed chains a run-time choice (the fence keeps it
+    // neutral for whichever op reads the state next).
+    uint32_t sbot = B::bottom();
+    if constexpr (MODE == MODE_MIXED) sbot = (a.erode_bits & 1) ? 255u : 0u;
 
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -811,14 +820,15 @@ __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int 
             uint8_t *sv = stage;            // RY x RX state
             uint8_t *sm = stage + RY * RX;  // RY x RX mask (clamped bodies)
             const uint32_t bot4 = B::bottom() * 0x01010101u;
+            const uint32_t sbot4 = sbot * 0x01010101u;
             const uint32_t top4 = B::top() * 0x01010101u;
             for (int i = threadIdx.x; i < NCH; i += 64 * NW) {
                 const int r = i / CH, c = i % CH;
                 const int y = ry0 + r, x = rx0 + 16 * c;
                 const bool yin = (unsigned)y < (unsigned)a.height;
                 const int64_t off = (int64_t)y * a.pitch + x;
-                uint4 cv = make_uint4(bot4, bot4, bot4, bot4);
-                uint4 cm = cv;
+                uint4 cv = make_uint4(sbot4, sbot4, sbot4, sbot4);
+                uint4 cm = make_uint4(bot4, bot4, bot4, bot4);
                 const bool whole = yin && x >= 0 && x + 16 <= a.width;
                 const bool none = !yin || x + 16 <= 0 || x >= a.width;
                 if (whole && ((uintptr_t)(src + off) & 15) == 0 &&
@@ -840,7 +850,7 @@ __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int 
                         for (int b = 0; b < 4; ++b) {
                             const int xb = x + 4 * q + b;
                             const bool in = yin && (unsigned)xb < (unsigned)a.width;
-                            const uint32_t pv = in ? (uint32_t)src[off + 4 * q + b] : B::bottom();
+                            const uint32_t pv = in ? (uint32_t)src[off + 4 * q + b] : sbot;
                             uint32_t pm = B::bottom();
                             if constexpr (MODE == MODE_GEODESIC)
                                 pm = in ? (uint32_t)msk[off + 4 * q + b] : B::bottom();
@@ -907,7 +917,7 @@ __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int 
                         const int y = ry0 + w * RPW + j + half * H;
                         const bool in = xin && (unsigned)y < (unsigned)a.height;
                         const int64_t off = (int64_t)y * a.pitch + x;
-                        vv[half] = in ? (uint32_t)src[off] : B::bottom();
+                        vv[half] = in ? (uint32_t)src[off] : sbot;
                         if constexpr (MODE == MODE_GEODESIC)
                             mm[half] = in ? (uint32_t)msk[off] : B::bottom();
                         else
@@ -973,6 +983,88 @@ __device__ __forceinline__ uint32_t chain_block_body_pk(const BlockArgs &a, int 
             if constexpr (D) changed |= (x ^ v[j][c]) & cmask[j][c];
             nv[j][c] = x;
         };
+
+        if constexpr (MODE == MODE_MIXED) {
+            // Each step takes the extremum of its own op (bit s of
+            // erode_bits: erosion).  The border fence after a step pins
+            // outside pixels to the neutral value of the op that reads the
+            // state next: m holds the dilation fence (255 inside, 0
+            // outside), the erosion fence is the same with each pixel's
+            // bits flipped (0 inside, 255 outside).  Steps go through one
+            // of four copies of the step body, chosen by a uniform branch
+            // on the ops of this step and the next.
+            const uint64_t eb = a.erode_bits;
+            auto row_pass_op = [&](auto op_tag, int j) {
+                using PO = PackedPick<decltype(op_tag)::value>;
+                const uint32_t left = lane_shift<DPP_WAVE_SHR1>(v[j][1]);
+                const uint32_t right = lane_shift<DPP_WAVE_SHL1>(v[j][0]);
+                h[j][0] = PO::pick3(left, v[j][0], v[j][1]);
+                h[j][1] = PO::pick3(v[j][0], v[j][1], right);
+            };
+            auto step_op = [&](int s, auto cur_tag, auto next_tag) {
+                using PC = PackedPick<decltype(cur_tag)::value>;
+                uint32_t nv[H][CW];
+                auto fin = [&](int j, int c, uint32_t x) {
+                    if constexpr (CLAMP) {
+                        if constexpr (decltype(next_tag)::value == OP_DILATE)
+                            x = PackedPick<OP_DILATE>::clamp(x, m[j][c]);
+                        else
+                            x = PackedPick<OP_ERODE>::clamp(x, m[j][c] ^ 0x00FF00FFu);
+                    }
+                    nv[j][c] = x;
+                };
+#pragma unroll
+                for (int c = 0; c < CW; ++c) {
+#pragma unroll
+                    for (int j = 1; j < H - 1; ++j) fin(j, c, PC::pick3(h[j - 1][c], h[j][c], h[j + 1][c]));
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int c = 0; c < CW; ++c) {
+                    const uint32_t up0 = __builtin_amdgcn_alignbit(h[H - 1][c], above[c], 16);
+                    const uint32_t dnl = __builtin_amdgcn_alignbit(below[c], h[0][c], 16);
+                    if constexpr (H == 1) {
+                        fin(0, c, PC::pick3(up0, h[0][c], dnl));
+                    } else {
+                        fin(0, c, PC::pick3(up0, h[0][c], h[1][c]));
+                        fin(H - 1, c, PC::pick3(h[H - 2][c], h[H - 1][c], dnl));
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < H; ++j)
+#pragma unroll
+                    for (int c = 0; c < CW; ++c) v[j][c] = nv[j][c];
+                if (s + 1 < busy) {
+                    row_pass_op(next_tag, 0);
+                    if constexpr (H > 1) row_pass_op(next_tag, H - 1);
+                    publish((s + 1) & 1);
+#pragma unroll
+                    for (int j = 1; j < H - 1; ++j) row_pass_op(next_tag, j);
+                }
+            };
+            using DIL = std::integral_constant<int, OP_DILATE>;
+            using ERO = std::integral_constant<int, OP_ERODE>;
+            if (eb & 1) {
+#pragma unroll
+                for (int j = 0; j < H; ++j) row_pass_op(ERO{}, j);
+            } else {
+#pragma unroll
+                for (int j = 0; j < H; ++j) row_pass_op(DIL{}, j);
+            }
+            publish(0);
+            for (int s = 0; s < busy; ++s) {
+                const bool ce = (eb >> s) & 1;
+                const bool ne = s + 1 < k ? ((eb >> (s + 1)) & 1) : ce;
+                if (ce) {
+                    if (ne) step_op(s, ERO{}, ERO{});
+                    else step_op(s, ERO{}, DIL{});
+                } else {
+                    if (ne) step_op(s, DIL{}, ERO{});
+                    else step_op(s, DIL{}, DIL{});
+                }
+            }
+            return;
+        }
 
 #pragma unroll
         for (int j = 0; j < H; ++j) row_pass(j);
@@ -1205,6 +1297,8 @@ __device__ __forceinline__ uint32_t chain_block_dispatch(
     uint8_t *stage) {
     constexpr int RX = lanes_per_group<G>() * CW;
     constexpr int RY = NW * RPW * G;
+    static_assert(MODE != MODE_MIXED || (std::is_same<T, uint8_t>::value && G == 1 && CW == 2 && RPW % 2 == 0),
+                  "mixed chains run on the packed u8 body");
     if constexpr (G == 2) {
         if constexpr (MODE == MODE_PLAIN) {
             const bool inside = rx0 >= 0 && ry0 >= 0 && rx0 + RX <= a.width && ry0 + RY <= a.height;
@@ -1215,7 +1309,7 @@ __device__ __forceinline__ uint32_t chain_block_dispatch(
         }
     } else if constexpr (std::is_same<T, uint8_t>::value && CW == 2 && RPW % 2 == 0) {
         // u8: two rows per register, packed half-precision extrema on encoded pixels
-        if constexpr (MODE == MODE_PLAIN) {
+        if constexpr (MODE == MODE_PLAIN || MODE == MODE_MIXED) {
             const bool inside = rx0 >= 0 && ry0 >= 0 && rx0 + RX <= a.width && ry0 + RY <= a.height;
             if (inside) return chain_block_body_pk<OP, MODE, false, DETECT, RPW, NW, AGENT_STORES, STAGED>(a, rx0, ry0, xch, stage);
             return chain_block_body_pk<OP, MODE, true, DETECT, RPW, NW, AGENT_STORES, STAGED>(a, rx0, ry0, xch, stage);

@@ -153,6 +153,9 @@ static LaunchFn pick_t(int op, int mode, bool detect, int fam) {
     return pick_fam<T, OP_ERODE, MODE_PLAIN, false>(fam);
 }
 
+// Mixed chains (a dilation or an erosion per step): u8, 128 x 128 regions.
+static LaunchFn pick_mixed() { return &launch_block<uint8_t, OP_DILATE, MODE_MIXED, false, FAM_128W>; }
+
 static LaunchFn pick_launch(gc_dtype d, int op, int mode, bool detect, int fam) {
     switch (d) {
         case GC_U8: return pick_t<uint8_t>(op, mode, detect, fam);

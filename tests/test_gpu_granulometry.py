@@ -81,6 +81,32 @@ def test_asf_in_place():
     assert np.array_equal(host(F), oracle.asf(f, 3))
 
 
+@pytest.mark.parametrize("shape", [(1, 1), (1, 300), (300, 1), (5, 7), (67, 129), (200, 517), (513, 385)])
+@pytest.mark.parametrize("s_max", [2, 7])
+def test_asf_u8_mixed_chains(shape, s_max):
+    """u8 ASF runs its short chains as one chain with a dilation or an
+    erosion per step, 32 steps per launch, so launches switch ops in their
+    middle and the border fence changes sides; with the window path off,
+    every chain of s_max = 7 (up to 14 steps) goes that way."""
+    f = image(shape, np.uint8, seed=7 * shape[0] + shape[1] + s_max)
+    ref = oracle.asf(f, s_max)
+    assert np.array_equal(host(gc.asf(dev(f), s_max)), ref)
+    gc.set_window_path(-1)
+    try:
+        F = dev(f)
+        gc.asf(F, s_max, out=F)   # in place as well
+        assert np.array_equal(host(F), ref)
+    finally:
+        gc.set_window_path(0)
+
+
+def test_asf_u8_mixed_and_window_chains():
+    """s_max = 16: the chains of 26 steps and more take the window path, the
+    shorter ones before and after them run as mixed chains."""
+    f = image((300, 410), np.uint8, seed=16)
+    assert np.array_equal(host(gc.asf(dev(f), 16)), oracle.asf(f, 16))
+
+
 def test_full_size_u8_pattern_spectrum_and_asf():
     f = workloads.operator_u8()
     check_granulometry(f, 11, "1024x1024 PS[0,11]")
