@@ -53,7 +53,8 @@ enum : int {
     MODE_GEODESIC = 0,   // mask read from memory (Eq. 3)
     MODE_PLAIN = 1,      // no mask (Eq. 1-2); the clamp only fences the border
     MODE_MIXED = 2,      // as MODE_PLAIN, each step a dilation or an erosion
-                         // (BlockArgs::erode_bits; packed u8 body only)
+                         // (BlockArgs::erode_bits; one lane group per wave;
+                         // launched for u8 and f32)
 };
 
 template <typename T> struct RegOf;
@@ -221,12 +222,23 @@ __device__ __forceinline__ void agent_store_reg(uint8_t *p, uint32_t v) { agent_
 __device__ __forceinline__ void agent_store_reg(float *p, float v) { agent_store(p, v); }
 __device__ __forceinline__ void agent_store_reg(double *p, double v) { agent_store(p, v); }
 
+// Mixed chains hold the dilation fence of a plain chain (top inside the
+// image, bottom outside); the erosion fence swaps the two values.
+__device__ __forceinline__ uint32_t erosion_fence(uint32_t m) { return 255u - m; }
+__device__ __forceinline__ float erosion_fence(float m) { return -m; }
+__device__ __forceinline__ double erosion_fence(double m) { return -m; }
+
 template <typename T, int OP, int MODE, bool CLAMP, bool DETECT, int CW, int RPW, int NW, bool AGENT_STORES = false>
 __device__ __forceinline__ uint32_t chain_block_body(const BlockArgs &a, int rx0, int ry0,
                                                      typename RegOf<T>::type (*xch)[NW][2][64 * CW]) {
     using R = typename RegOf<T>::type;
     using B = Bounds<R, OP>;
     using P = Pick<OP>;
+    static_assert(MODE != MODE_MIXED || OP == OP_DILATE, "mixed chains hold the dilation form of the fence");
+    // State outside the image starts at the neutral value of the first
+    // step's op (for mixed chains a run-time choice).
+    R sbot = B::bottom();
+    if constexpr (MODE == MODE_MIXED) sbot = (a.erode_bits & 1) ? Bounds<R, OP_ERODE>::bottom() : B::bottom();
 
     const int lane = threadIdx.x & 63;
     // wave index, known uniform: keeps the exchange branches scalar
@@ -278,7 +290,7 @@ __device__ __forceinline__ uint32_t chain_block_body(const BlockArgs &a, int rx0
                 const int x = rx0 + lane * CW + c;
                 const bool in = yin && (unsigned)x < (unsigned)a.width;
                 const int64_t off = (int64_t)y * a.pitch + x;
-                v[r][c] = in ? to_reg(src[off]) : B::bottom();
+                v[r][c] = in ? to_reg(src[off]) : sbot;
                 if constexpr (CLAMP) {
                     if constexpr (MODE == MODE_GEODESIC)
                         m[r][c] = in ? to_reg(msk[off]) : B::bottom();
@@ -381,6 +393,91 @@ __device__ __forceinline__ uint32_t chain_block_body(const BlockArgs &a, int rx0
                 nv[r][c] = x;
             }
         };
+
+        if constexpr (MODE == MODE_MIXED) {
+            // Each step takes the extremum of its own op (bit s of
+            // erode_bits: erosion); after a step the border fence pins
+            // outside pixels to the neutral value of the op that reads the
+            // state next.  Four copies of the step body, chosen by a uniform
+            // branch on the ops of this step and the next.
+            const uint64_t eb = a.erode_bits;
+            auto row_pass_op = [&](auto op_tag, int r) {
+                using PO = Pick<decltype(op_tag)::value>;
+                const R left = lane_shift<DPP_WAVE_SHR1>(v[r][CW - 1]);
+                const R right = lane_shift<DPP_WAVE_SHL1>(v[r][0]);
+                if constexpr (CW == 1) {
+                    h[r][0] = PO::pick(PO::pick(left, v[r][0]), right);
+                } else if constexpr (CW == 2) {
+                    const R t = PO::pick(v[r][0], v[r][1]);
+                    h[r][0] = PO::pick(t, left);
+                    h[r][1] = PO::pick(t, right);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < CW; ++c) {
+                        const R l = c == 0 ? left : v[r][c - 1];
+                        const R rr = c == CW - 1 ? right : v[r][c + 1];
+                        h[r][c] = PO::pick(PO::pick(v[r][c], rr), l);
+                    }
+                }
+            };
+            auto step_op = [&](int s, auto cur_tag, auto next_tag) {
+                using PC = Pick<decltype(cur_tag)::value>;
+                R nv[RPW][CW];
+                auto col = [&](int r) {
+#pragma unroll
+                    for (int c = 0; c < CW; ++c) {
+                        const R up = r == 0 ? above[c] : h[r - 1][c];
+                        const R dn = r == RPW - 1 ? below[c] : h[r + 1][c];
+                        R x = PC::pick(PC::pick(up, h[r][c]), dn);
+                        if constexpr (CLAMP) {
+                            if constexpr (decltype(next_tag)::value == OP_DILATE)
+                                x = Pick<OP_DILATE>::clamp(x, m[r][c]);
+                            else
+                                x = Pick<OP_ERODE>::clamp(x, erosion_fence(m[r][c]));
+                        }
+                        nv[r][c] = x;
+                    }
+                };
+#pragma unroll
+                for (int r = 1; r < RPW - 1; ++r) col(r);
+                __builtin_amdgcn_sched_barrier(0);
+                col(0);
+                if constexpr (RPW > 1) col(RPW - 1);
+#pragma unroll
+                for (int r = 0; r < RPW; ++r)
+#pragma unroll
+                    for (int c = 0; c < CW; ++c) v[r][c] = nv[r][c];
+                if (s + 1 < busy) {
+                    row_pass_op(next_tag, 0);
+                    if constexpr (RPW > 1) row_pass_op(next_tag, RPW - 1);
+                    publish((s + 1) & 1);
+#pragma unroll
+                    for (int r = 1; r < RPW - 1; ++r) row_pass_op(next_tag, r);
+                }
+            };
+            using DIL = std::integral_constant<int, OP_DILATE>;
+            using ERO = std::integral_constant<int, OP_ERODE>;
+            if (eb & 1) {
+#pragma unroll
+                for (int r = 0; r < RPW; ++r) row_pass_op(ERO{}, r);
+            } else {
+#pragma unroll
+                for (int r = 0; r < RPW; ++r) row_pass_op(DIL{}, r);
+            }
+            publish(0);
+            for (int s = 0; s < busy; ++s) {
+                const bool ce = (eb >> s) & 1;
+                const bool ne = s + 1 < k ? ((eb >> (s + 1)) & 1) : ce;
+                if (ce) {
+                    if (ne) step_op(s, ERO{}, ERO{});
+                    else step_op(s, ERO{}, DIL{});
+                } else {
+                    if (ne) step_op(s, DIL{}, ERO{});
+                    else step_op(s, DIL{}, DIL{});
+                }
+            }
+            return;
+        }
 
 #pragma unroll
         for (int r = 0; r < RPW; ++r) row_pass(r);
@@ -1297,8 +1394,7 @@ __device__ __forceinline__ uint32_t chain_block_dispatch(
     uint8_t *stage) {
     constexpr int RX = lanes_per_group<G>() * CW;
     constexpr int RY = NW * RPW * G;
-    static_assert(MODE != MODE_MIXED || (std::is_same<T, uint8_t>::value && G == 1 && CW == 2 && RPW % 2 == 0),
-                  "mixed chains run on the packed u8 body");
+    static_assert(MODE != MODE_MIXED || G == 1, "mixed chains run on one lane group per wave");
     if constexpr (G == 2) {
         if constexpr (MODE == MODE_PLAIN) {
             const bool inside = rx0 >= 0 && ry0 >= 0 && rx0 + RX <= a.width && ry0 + RY <= a.height;
@@ -1316,7 +1412,7 @@ __device__ __forceinline__ uint32_t chain_block_dispatch(
         } else {
             return chain_block_body_pk<OP, MODE, true, DETECT, RPW, NW, AGENT_STORES, STAGED>(a, rx0, ry0, xch, stage);
         }
-    } else if constexpr (MODE == MODE_PLAIN) {
+    } else if constexpr (MODE == MODE_PLAIN || MODE == MODE_MIXED) {
         const bool inside = rx0 >= 0 && ry0 >= 0 && rx0 + RX <= a.width && ry0 + RY <= a.height;
         if (inside) return chain_block_body<T, OP, MODE, false, DETECT, CW, RPW, NW, AGENT_STORES>(a, rx0, ry0, xch);
         return chain_block_body<T, OP, MODE, true, DETECT, CW, RPW, NW, AGENT_STORES>(a, rx0, ry0, xch);

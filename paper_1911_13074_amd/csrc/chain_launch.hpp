@@ -153,8 +153,15 @@ static LaunchFn pick_t(int op, int mode, bool detect, int fam) {
     return pick_fam<T, OP_ERODE, MODE_PLAIN, false>(fam);
 }
 
-// Mixed chains (a dilation or an erosion per step): u8, 128 x 128 regions.
-static LaunchFn pick_mixed() { return &launch_block<uint8_t, OP_DILATE, MODE_MIXED, false, FAM_128W>; }
+// Mixed chains (a dilation or an erosion per step): 128 x 128 regions, u8
+// and f32 (the f64 body would spill registers with four step copies).
+static LaunchFn pick_mixed(gc_dtype d) {
+    switch (d) {
+        case GC_U8: return &launch_block<uint8_t, OP_DILATE, MODE_MIXED, false, FAM_128W>;
+        case GC_F32: return &launch_block<float, OP_DILATE, MODE_MIXED, false, FAM_128W>;
+        default: return nullptr;
+    }
+}
 
 static LaunchFn pick_launch(gc_dtype d, int op, int mode, bool detect, int fam) {
     switch (d) {

@@ -513,16 +513,16 @@ static int copy_batch(void *dst, const void *src, const gc_shape &s, size_t es, 
     return GC_OK;
 }
 
-// MODE_MIXED (u8 only): erode_steps[i] != 0 makes step i an erosion, else a
-// dilation; op is unused.
+// MODE_MIXED (u8 and f32): erode_steps[i] != 0 makes step i an erosion,
+// else a dilation; op is unused.
 static int run_chain(gc_dtype dtype, int op, int mode, const void *src, const void *mask, void *out,
                      const gc_shape &s, int64_t n, void *stream, void *fixed_ws = nullptr,
                      size_t fixed_bytes = 0, int32_t n_images = 1, int64_t image_stride = 0,
                      const uint8_t *erode_steps = nullptr) {
     if (n < 0) return fail(GC_ERR_INVALID_ARG, "n_steps < 0");
     const bool mixed = mode == MODE_MIXED;
-    if (mixed && (dtype != GC_U8 || erode_steps == nullptr))
-        return fail(GC_ERR_UNSUPPORTED, "mixed chains take u8 images and a list of steps");
+    if (mixed && (dtype == GC_F64 || erode_steps == nullptr))
+        return fail(GC_ERR_UNSUPPORTED, "mixed chains take u8 or f32 images and a list of steps");
     const bool empty = s.width == 0 || s.height == 0 || n_images == 0;
     const size_t es = elem_size(dtype);
     hipStream_t st = (hipStream_t)stream;
@@ -604,7 +604,7 @@ static int run_chain(gc_dtype dtype, int op, int mode, const void *src, const vo
         if (mixed)
             for (int j = 0; j < ki; ++j)
                 if (erode_steps[step0 + j]) a.erode_bits |= uint64_t(1) << j;
-        LaunchFn fn = mixed ? pick_mixed() : pick_launch(dtype, op, mode, false, p.fam);
+        LaunchFn fn = mixed ? pick_mixed(dtype) : pick_launch(dtype, op, mode, false, p.fam);
         const int pr = hook ? prof_begin(st, ki) : -1;
         fn(a, g.tiles * n_images, st);
         if (hook) prof_end(pr, st);
@@ -921,9 +921,9 @@ static int run_granulometry_t(gc_dtype dtype, const T *f, const gc_shape &s, int
 // phi_s(gamma_s(...)) as one list of plain chains; consecutive chains of the
 // same direction are one chain of the summed length (delta_a of delta_b is
 // delta_{a+b} by Eq. 4), so the sequence runs as E1 D2 E3 D4 ... D2S ES.
-// u8: consecutive chains shorter than 64 steps that do not take the window
-// path run as one mixed chain (a dilation or an erosion per step), 32 steps
-// per launch whatever the chains' lengths.
+// u8 and f32: consecutive chains shorter than 64 steps that do not take the
+// window path run as one mixed chain (a dilation or an erosion per step),
+// 32 steps per launch whatever the chains' lengths.
 static int run_asf(gc_dtype dtype, const void *f, void *out, const gc_shape &s, int s_max, void *stream) {
     const size_t es = elem_size(dtype);
     if (s_max == 0) return copy_image(out, f, s, es, (hipStream_t)stream);
@@ -941,7 +941,7 @@ static int run_asf(gc_dtype dtype, const void *f, void *out, const gc_shape &s, 
         push(OP_ERODE, sz);
     }
     const void *cur = f;
-    std::vector<uint8_t> run;   // u8: steps of the pending mixed chain (1 = erosion)
+    std::vector<uint8_t> run;   // steps of the pending mixed chain (1 = erosion)
     auto flush = [&]() -> int {
         if (run.empty()) return GC_OK;
         const int rc = run_chain(dtype, OP_DILATE, MODE_MIXED, cur, nullptr, out, s, (int64_t)run.size(), stream,
@@ -951,7 +951,7 @@ static int run_asf(gc_dtype dtype, const void *f, void *out, const gc_shape &s, 
         return rc;
     };
     for (const auto &c : seq) {
-        if (dtype == GC_U8 && c.second < 64 && !window_path(dtype, s, c.second)) {
+        if (dtype != GC_F64 && c.second < 64 && !window_path(dtype, s, c.second)) {
             run.insert(run.end(), (size_t)c.second, (uint8_t)(c.first == OP_ERODE));
             if (run.size() >= ((size_t)1 << 16)) {
                 const int rc = flush();

@@ -81,14 +81,16 @@ def test_asf_in_place():
     assert np.array_equal(host(F), oracle.asf(f, 3))
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("shape", [(1, 1), (1, 300), (300, 1), (5, 7), (67, 129), (200, 517), (513, 385)])
 @pytest.mark.parametrize("s_max", [2, 7])
-def test_asf_u8_mixed_chains(shape, s_max):
-    """u8 ASF runs its short chains as one chain with a dilation or an
-    erosion per step, 32 steps per launch, so launches switch ops in their
-    middle and the border fence changes sides; with the window path off,
-    every chain of s_max = 7 (up to 14 steps) goes that way."""
-    f = image(shape, np.uint8, seed=7 * shape[0] + shape[1] + s_max)
+def test_asf_mixed_chains(dtype, shape, s_max):
+    """u8 and f32 ASF run their short chains as one chain with a dilation
+    or an erosion per step, 32 steps per launch, so launches switch ops in
+    their middle and the border fence changes sides (f64 runs each chain on
+    its own); with the window path off, every chain of s_max = 7 (up to 14
+    steps) goes that way."""
+    f = image(shape, dtype, seed=7 * shape[0] + shape[1] + s_max)
     ref = oracle.asf(f, s_max)
     assert np.array_equal(host(gc.asf(dev(f), s_max)), ref)
     gc.set_window_path(-1)
@@ -100,11 +102,13 @@ def test_asf_u8_mixed_chains(shape, s_max):
         gc.set_window_path(0)
 
 
-def test_asf_u8_mixed_and_window_chains():
-    """s_max = 16: the chains of 26 steps and more take the window path, the
-    shorter ones before and after them run as mixed chains."""
-    f = image((300, 410), np.uint8, seed=16)
-    assert np.array_equal(host(gc.asf(dev(f), 16)), oracle.asf(f, 16))
+@pytest.mark.parametrize("dtype", [np.uint8, np.float32])
+def test_asf_mixed_and_window_chains(dtype):
+    """s_max = 20: the chains long enough for the window path (26 steps and
+    more for u8, 34 for f32) take it, the shorter ones before and after them
+    run as mixed chains."""
+    f = image((300, 410), dtype, seed=16)
+    assert np.array_equal(host(gc.asf(dev(f), 20)), oracle.asf(f, 20))
 
 
 def test_full_size_u8_pattern_spectrum_and_asf():
